@@ -1,0 +1,373 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the paper's
+worked example (Sec. 4.1 figure walk-through, the two metadata tables, the
+displayed bit series of Sec. 4.3), closed forms of rANS on uniform tables,
+Lemma 3.1, information-theoretic size bounds, and exhaustive enumeration on
+tiny parameters.
+"""
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests import _fmt
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_recoil_example.json")
+
+
+def _rng_symbols(seed, n, A, dtype=np.uint8):
+    return (synth.splitmix64(seed, 0, n) % np.uint64(A)).astype(dtype)
+
+
+# ---------------------------------------------------------------------------
+# Closed forms (Eq. 1 and Eq. 3 with f = 1 and n = 8: each symbol appends one byte)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lanes", [1, 2, 3, 32])
+def test_uniform_closed_form_words(orc, lanes):
+    """With 256 symbols of f = 1 at n = 8 every encode step is x -> 256 x + s.
+
+    Starting from L = 2^16 a lane emits its first symbol alone before its
+    second symbol, and then the two bytes s_{2m-1}, s_{2m} before symbol 2m+1;
+    within a group, lanes emit in increasing order (Sec. 2.2).
+    """
+    N = 40 * lanes + 3
+    s = _rng_symbols(11 + lanes, N, 256)
+    p = orc.params(lanes=lanes, quant_bits=8, alphabet=256)
+    enc = orc.encode(s, p, 1, freq=np.ones(256, dtype=np.uint32))
+    words = _fmt.parse(enc.container())["words"]
+    expect = []
+    groups = -(-N // lanes)
+    for m in range(1, groups, 2):                       # emitting groups 1, 3, 5, ...
+        for j in range(lanes):
+            if m * lanes + j >= N:
+                continue
+            local = s[j::lanes]
+            if m == 1:
+                expect.append(int(local[0]))
+            else:
+                expect.append((int(local[m - 2]) << 8) | int(local[m - 1]))
+    assert words.tolist() == expect
+    dec = orc.Decoder(enc.container())
+    assert np.array_equal(dec.serial(), s)
+
+
+def test_uniform_size_is_exact(orc):
+    """f = 2^(n-8) for all 256 symbols: every symbol costs 8 bits.
+
+    At n = 8 each step is x -> 256 x + s and at n > 8 it is
+    256 x - 255 (x mod f) + s f; both are 256 x to within a factor
+    1 + 2^n / x, so the code length is 8 N up to a small fraction of a bit.
+    """
+    for n in (8, 10, 12):
+        N, W = 4096, 4
+        s = _rng_symbols(n, N, 256)
+        f = np.full(256, 1 << (n - 8), dtype=np.uint32)
+        enc = orc.encode(s, orc.params(lanes=W, quant_bits=n), 1, freq=f)
+        c = _fmt.parse(enc.container())
+        # 16 B + sum_j log2(final_j) - 16 W is the code length (every lane starts at 2^16).
+        total = 16 * c["B"] + sum(math.log2(int(x)) for x in c["final"]) - 16 * W
+        # Per step |log2(x'/x) - 8| <= log2(e) * 2^(n-8) / x with x >= L = 2^16.
+        assert abs(total - 8 * N) <= N * 1.4427 * 2.0 ** (n - 8) / 2.0 ** 16
+
+
+# ---------------------------------------------------------------------------
+# Quantisation
+# ---------------------------------------------------------------------------
+
+def test_quantize_properties(orc):
+    counts = np.array([0, 5, 1, 0, 100, 7, 3, 0, 1], dtype=np.uint64)
+    for n in (4, 8, 11, 16):
+        f = orc.quantize(counts, n)
+        assert int(f.sum()) == 1 << n
+        assert all((f[i] > 0) == (counts[i] > 0) for i in range(len(counts)))
+    # Proportional counts quantise exactly.
+    f = orc.quantize(np.array([1, 1, 2, 4], dtype=np.uint64), 3)
+    assert f.tolist() == [1, 1, 2, 4]
+    with pytest.raises(orc.OracleError):
+        orc.quantize(np.ones(9, dtype=np.uint64), 3)       # 9 symbols > 2^3 slots
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Sec. 4.1, Tables 1-2, Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def _golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def test_backward_scan_example(orc):
+    g = _golden()
+    W = g["lanes"]
+    events = [(e["offset"] - 1, e["encoder"] - 1, e["symbol"] - 1, 1000 + e["symbol"])
+              for e in g["events_in_word_order"]]
+    split = g["split_offset"] - 1
+    states, idx, valid = orc.scan_events(events, W, split)
+    assert valid
+    assert (idx + 1).tolist() == g["expected_recorded_symbol_per_encoder"]
+    assert (states - 1000).tolist() == g["expected_recorded_symbol_per_encoder"]
+    groups = -(-(idx + 1) // W)                          # 1-based group id = ceil(i / W)
+    assert groups.tolist() == g["expected_group_ids"]
+    assert int(groups.max()) == g["expected_anchor"]
+    assert (groups - groups.max()).tolist() == g["expected_group_differences"]
+    lo, hi = g["synchronisation_section"]
+    assert int(idx.min()) + 1 == lo and int(idx.max()) + 1 == hi
+
+
+def test_metadata_tables_and_series_bits(orc):
+    """Tables 1 and 2 and the displayed series, through the container writer.
+
+    With B = 10 words, G = 9 groups (N = 36) and M = 2 threads, the expected
+    offset ceil(B/M) = 5 and the expected max group id ceil(G/M) = 5 match the
+    'Expected' column of Table 1.
+    """
+    g = _golden()
+    W = g["lanes"]
+    p = orc.params(lanes=W, quant_bits=2, alphabet=4, l_bits=16, b_bits=16)
+    idx = np.array(g["expected_recorded_symbol_per_encoder"]) - 1
+    states = np.array([0x1111, 0x2222, 0x3333, 0x4444], dtype=np.uint32)
+    c = orc.assemble(p, 36, [1, 1, 1, 1], np.arange(10), [1 << 16] * W,
+                     [g["split_offset"] - 1], states[None, :], idx[None, :])
+    meta = _fmt.parse(c)["meta"]
+    t1 = g["split_point_metadata"]
+    d_off = t1["bitstream_offset"]["difference"]
+    d_grp = t1["max_symbol_group_id"]["difference"]
+    # Signed series: 5-bit (width-1) field, then sign + magnitude per value.
+    expect = "00000" + ("1" if d_off < 0 else "0") + format(abs(d_off), "b")
+    expect += "00000" + ("1" if d_grp < 0 else "0") + format(abs(d_grp), "b")
+    expect += "".join(format(int(x), "016b") for x in states)
+    expect += g["group_difference_series_bits"]
+    assert _fmt.bits(meta, len(expect)) == expect
+    assert len(meta) == -(-len(expect) // 8)
+
+
+def test_series_example_and_roundtrip(orc):
+    g = _golden()
+    data, nbits = orc.series_pack([1, 0, 1, 0], 4, signed=False)
+    assert nbits == 8 and _fmt.bits(data) == g["group_difference_series_bits"]
+    data, nbits = orc.series_pack([0, 0, 0], 4, signed=False)
+    assert _fmt.bits(data, nbits) == "0000000"           # zero still takes one bit
+    vals = [5, -3, 0, 1 << 20, -(1 << 31)]
+    data, nbits = orc.series_pack(vals, 5, signed=True)
+    assert nbits == 5 + len(vals) * (1 + 32)
+    back, used = orc.series_unpack(data, len(vals), 5, signed=True)
+    assert back.tolist() == vals and used == nbits
+    with pytest.raises(orc.OracleError):
+        orc.series_pack([1 << 16], 4, signed=False)      # 17 bits do not fit a 4-bit width field
+
+
+def _find_figure6_sequence(orc):
+    """A seeded sequence whose encoding holds the Figure 6 event pattern (W = 4)."""
+    p = orc.params(lanes=4, quant_bits=3, alphabet=3, l_bits=4, b_bits=4)
+    f = np.array([1, 2, 5], dtype=np.uint32)
+    want = (np.array(_golden()["expected_recorded_symbol_per_encoder"]) - 1).tolist()
+    for seed in range(5000):
+        s = _rng_symbols(seed, 40, 3)
+        enc = orc.encode(s, p, 1, freq=f)
+        ev = enc.events()
+        for k in np.nonzero(ev[:, 2] == max(want))[0]:
+            cand = enc.candidate_at(int(k))
+            if cand is not None and cand.indices.tolist() == want and 11 - 1 in ev[:k, 2]:
+                return p, f, s, enc, cand
+    raise AssertionError("no sequence with the example's pattern")
+
+
+def test_synchronisation_phase_example(orc):
+    """Decoding from the example split: the sync phase yields s16, s14, s12, s11, s10, s9
+    and skips s15 and s13 (1-based), then continues normally."""
+    g = _golden()
+    p, f, s, enc, cand = _find_figure6_sequence(orc)
+    c = orc.assemble(p, len(s), f, _fmt.parse(enc.container())["words"], _fmt.parse(enc.container())["final"],
+                     [cand.pos], cand.states[None, :], cand.indices[None, :])
+    dec = orc.Decoder(c)
+    assert dec.threads == 2
+    _, trace = dec.thread_trace(1)
+    lo, hi = g["synchronisation_section"]
+    in_sync = [int(i) + 1 for i in trace if lo <= int(i) + 1 <= hi]
+    assert sorted(in_sync, reverse=True) == g["sync_phase_decoded"]
+    assert not set(g["sync_phase_skipped"]) & set(in_sync)
+    # After the section the thread decodes every index down to 1 exactly once.
+    below = [int(i) + 1 for i in trace if int(i) + 1 < lo]
+    assert sorted(below) == list(range(1, lo))
+    assert np.array_equal(dec.all(), s)
+    assert np.array_equal(dec.all(aligned=True), s)
+
+
+# ---------------------------------------------------------------------------
+# Lemma 3.1, sizes, heuristic and combining on a realistic stream
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c0(orc):
+    spec = synth.c0_spec()
+    s = spec.generate()
+    p = orc.params(lanes=spec.lanes, quant_bits=spec.quant_bits)
+    enc = orc.encode(s, p, spec.splits)
+    return spec, s, p, enc, enc.container()
+
+
+def test_lemma_3_1_states_bounded(orc, c0):
+    spec, s, p, enc, c = c0
+    ev = enc.events()
+    assert (ev[:, 3] >= 1).all() and (ev[:, 3] < (1 << 16)).all()
+    for k in range(1, enc.threads):
+        sp = enc.split(k)
+        assert (sp.states >= 1).all() and (sp.states < (1 << 16)).all()
+
+
+def test_size_against_entropy(orc, c0):
+    """16 B + sum log2(final) - 16 W equals the ideal code length up to rounding."""
+    spec, s, p, enc, c = c0
+    hdr = _fmt.parse(c)
+    f = orc.quantize(np.bincount(s, minlength=256).astype(np.uint64), spec.quant_bits)
+    ideal = float(-np.log2(f[s].astype(np.float64) / (1 << spec.quant_bits)).sum())
+    measured = 16 * hdr["B"] + float(np.log2(hdr["final"].astype(np.float64)).sum()) - 16 * spec.lanes
+    assert abs(measured - ideal) / ideal < 1e-3
+    emp = np.bincount(s, minlength=256) / len(s)
+    h = -(emp[emp > 0] * np.log2(emp[emp > 0])).sum()
+    assert 16 * hdr["B"] / len(s) < h * 1.01 + 0.01
+
+
+def test_heuristic_properties(orc, c0):
+    spec, s, p, enc, c = c0
+    dec = orc.Decoder(c)
+    assert dec.threads == spec.splits
+    ranges = [dec.thread_range(t) for t in range(1, dec.threads + 1)]
+    assert ranges[0][0] == 0 and ranges[-1][1] == len(s)
+    assert all(ranges[k][1] == ranges[k + 1][0] for k in range(len(ranges) - 1))
+    sizes = np.array([hi - lo for lo, hi in ranges])
+    assert sizes.max() / sizes.mean() < 1.10
+
+
+def test_metadata_bytes_per_split_band(orc, c0):
+    """Paper Tables 5/6: Recoil metadata is about 75-88 bytes per split at W = 32."""
+    spec, s, p, enc, c = c0
+    per_split = orc.info(c).metadata_bytes / (spec.splits - 1)
+    assert 60 <= per_split <= 100
+
+
+def test_round_trip_and_every_thread(orc, c0):
+    spec, s, p, enc, c = c0
+    dec = orc.Decoder(c)
+    assert np.array_equal(dec.serial(), s)
+    assert np.array_equal(dec.all(fill=0xAB), s)
+    assert np.array_equal(dec.all(aligned=True, fill=0xCD), s)
+    assert np.array_equal(dec.all(workers=4), s)
+
+
+@pytest.mark.parametrize("target", [128, 100, 64, 16, 3, 1])
+def test_combine(orc, c0, target):
+    spec, s, p, enc, c = c0
+    cc = orc.combine(c, target)
+    d0, d1 = orc.Decoder(c), orc.Decoder(cc)
+    step = -(-spec.splits // target)
+    assert d1.threads == -(-spec.splits // step)
+    b0 = {d0.thread_range(t)[1] for t in range(1, d0.threads + 1)}
+    b1 = {d1.thread_range(t)[1] for t in range(1, d1.threads + 1)}
+    assert b1 <= b0                                      # kept split points are original ones
+    assert np.array_equal(d1.all(fill=0x11), s)
+    assert np.array_equal(d1.all(aligned=True), s)
+    info0, info1 = orc.info(c), orc.info(cc)
+    assert info1.n_words == info0.n_words                # the bitstream is untouched
+    assert _fmt.parse(cc)["words"].tobytes() == _fmt.parse(c)["words"].tobytes()
+
+
+# ---------------------------------------------------------------------------
+# Special cases
+# ---------------------------------------------------------------------------
+
+def test_single_lane_sync_section_is_one_symbol(orc):
+    """W = 1 (the non-interleaved case of Sec. 3): a split is (state, offset, index)."""
+    s = _rng_symbols(5, 3000, 16)
+    p = orc.params(lanes=1, quant_bits=8, alphabet=16)
+    enc = orc.encode(s, p, 8)
+    assert enc.threads == 8
+    for k in range(1, enc.threads):
+        sp = enc.split(k)
+        assert sp.imax == sp.imin
+    assert np.array_equal(orc.Decoder(enc.container()).all(), s)
+
+
+def test_one_thread_equals_serial(orc):
+    s = _rng_symbols(6, 5000, 200)
+    enc = orc.encode(s, orc.params(lanes=32, quant_bits=10), 1)
+    d = orc.Decoder(enc.container())
+    assert d.threads == 1 and orc.info(enc.container()).metadata_bytes == 0
+    assert np.array_equal(d.all(), d.serial())
+
+
+@pytest.mark.parametrize("N", [0, 1, 5, 31])
+def test_fewer_symbols_than_lanes(orc, N):
+    s = _rng_symbols(7, N, 10)
+    enc = orc.encode(s, orc.params(lanes=32, quant_bits=8, alphabet=10), 16)
+    assert enc.threads == 1
+    d = orc.Decoder(enc.container())
+    assert np.array_equal(d.all(), s)
+    assert np.array_equal(d.serial(), s)
+
+
+def test_wide_symbols(orc):
+    s = _rng_symbols(8, 20000, 4096, np.uint16)
+    p = orc.params(lanes=32, quant_bits=12, symbol_bytes=2, alphabet=4096)
+    enc = orc.encode(s, p, 10)
+    d = orc.Decoder(enc.container())
+    assert d.threads == 10
+    assert np.array_equal(d.all(), s) and np.array_equal(d.all(aligned=True), s)
+
+
+# ---------------------------------------------------------------------------
+# Brute force on tiny parameters: every sequence, every single split point
+# ---------------------------------------------------------------------------
+
+def _all_single_splits_decode(orc, p, f, s):
+    enc = orc.encode(s, p, 1, freq=f)
+    c = enc.container()
+    hdr = _fmt.parse(c)
+    assert np.array_equal(orc.Decoder(c).serial(), s)
+    cands = []
+    for k in range(hdr["B"]):
+        cand = enc.candidate_at(k)
+        if cand is None:
+            continue
+        cands.append(cand)
+        cc = orc.assemble(p, len(s), f, hdr["words"], hdr["final"], [cand.pos],
+                          cand.states[None, :], cand.indices[None, :])
+        d = orc.Decoder(cc)
+        assert np.array_equal(d.all(fill=255), s), (s.tolist(), cand.pos)
+        assert np.array_equal(d.all(aligned=True, fill=255), s), (s.tolist(), cand.pos)
+    # Every pair of candidates as a two-split set.
+    for a, b in itertools.combinations(cands, 2):
+        if b.imin < a.imin:
+            continue
+        cc = orc.assemble(p, len(s), f, hdr["words"], hdr["final"], [a.pos, b.pos],
+                          np.stack([a.states, b.states]), np.stack([a.indices, b.indices]))
+        assert np.array_equal(orc.Decoder(cc).all(fill=255), s), (s.tolist(), a.pos, b.pos)
+    return len(cands)
+
+
+@pytest.mark.parametrize("lanes,length", [(1, 7), (2, 7), (3, 7)])
+def test_brute_force_tiny_parameters(orc, lanes, length):
+    """L = 2^4, b = 4, n = 3, alphabet 3: all sequences of the given length."""
+    p = orc.params(lanes=lanes, quant_bits=3, alphabet=3, l_bits=4, b_bits=4)
+    f = np.array([1, 2, 5], dtype=np.uint32)
+    total = 0
+    for seq in itertools.product(range(3), repeat=length):
+        total += _all_single_splits_decode(orc, p, f, np.array(seq, dtype=np.uint8))
+    assert total > 0
+
+
+def test_brute_force_real_parameters_skewed_binary(orc):
+    """32-bit states, L = 2^16, b = 16, n = 12, f = (1, 4095): all binary sequences of length 12."""
+    p = orc.params(lanes=2, quant_bits=12, alphabet=2)
+    f = np.array([1, 4095], dtype=np.uint32)
+    total = 0
+    for seq in itertools.product(range(2), repeat=12):
+        total += _all_single_splits_decode(orc, p, f, np.array(seq, dtype=np.uint8))
+    assert total > 0
