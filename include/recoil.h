@@ -1,0 +1,197 @@
+/*
+ * librecoil -- parallel rANS decoding with decoder-adaptive scalability on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lin et al., "Recoil: Parallel rANS Decoding with Decoder-Adaptive
+ * Scalability", ICPP 2023. One interleaved rANS bitstream is encoded once; split
+ * points are recorded as metadata (per-lane 16-bit intermediate states taken at
+ * renormalisation points, plus their symbol indices); the metadata can later be
+ * cut down to any smaller number of splits without touching the bitstream; the
+ * decoder starts one independent decode unit per split.
+ *
+ * Terminology used throughout this header:
+ *   N        number of symbols; symbols are uint8 or uint16
+ *   W        interleaved lanes (32 or 64 on the GPU)
+ *   n        quantisation bits: the frequency table f sums to 2^n (Def. 2.1)
+ *   L, b     renormalisation lower bound 2^16 and word size 16 bits (Table "rANS parameters")
+ *   B        number of 16-bit words in the bitstream
+ *   M        number of decode units ("splits"); M - 1 split points are stored
+ *   group    symbols gW .. gW+W-1; symbol i belongs to lane i mod W
+ *
+ * Ownership: host objects (blobs, plans, batches, servers) are created and
+ * freed by the library. All device memory is owned by the caller and passed in
+ * as plain device pointers; decode calls never allocate, never synchronise and
+ * only enqueue work on the given HIP stream.
+ *
+ * Errors: every call returns a recoil_status (0 = success, < 0 = error);
+ * recoil_last_error() returns a thread-local message for the last failure.
+ * Corruption that can only be detected while decoding on the device is
+ * reported through a caller-owned uint32 error word (see recoil_decode).
+ *
+ * Container byte layout ("RCL1", little-endian; produced by recoil_blob_serialize):
+ *   0  char[4] magic "RCL1"        4  u16 version (1)
+ *   6  u8 W                        7  u8 n
+ *   8  u8 symbol bytes (1|2)       9  u8 log2 L (16)     10 u8 b (16)   11 u8 0
+ *   12 u32 alphabet size A         16 u64 N              24 u64 B
+ *   32 u32 M                       36 u32 table bytes    40 u32 metadata bytes  44 u32 0
+ *   48 table: f[0..A) as an unsigned bit series with a 5-bit width field
+ *      final states: W x u32 (the encoder's last states, transmitted explicitly, Sec. 3.1)
+ *      metadata (Sec. 4.3), one MSB-first bit stream, zero-padded to a byte:
+ *        signed series (5-bit width field) of (p_k + 1) - k * ceil(B/M), k = 1..M-1
+ *        signed series (5-bit width field) of (g_k + 1) - k * ceil(G/M)
+ *        per split point k: W x 16-bit states, then an unsigned series
+ *        (4-bit width field) of g_k - (group of lane j's recorded symbol)
+ *      words: B x u16
+ *   where p_k is the word position of split point k, g_k its largest symbol
+ *   group (the anchor, 0-based) and G = ceil(N/W). A bit series is a
+ *   (width - 1) field followed by one value of `width` bits per element (signed
+ *   series put a sign bit before each magnitude); width = max(1, bit length of
+ *   the largest magnitude).
+ */
+#ifndef RECOIL_H
+#define RECOIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t recoil_status;
+enum {
+    RECOIL_OK = 0,
+    RECOIL_ERR_INVALID_ARG = -1,    /* a NULL pointer, a size or a parameter out of range */
+    RECOIL_ERR_INFEASIBLE = -2,     /* more distinct symbols than 2^n, or metadata that does not fit */
+    RECOIL_ERR_CORRUPT = -3,        /* container failed validation */
+    RECOIL_ERR_UNSUPPORTED = -4,    /* valid container outside what the GPU decoder handles */
+    RECOIL_ERR_BUFFER_TOO_SMALL = -5,
+    RECOIL_ERR_HIP = -6,            /* a HIP runtime call failed */
+    RECOIL_ERR_ALIGNMENT = -7,      /* a device pointer is not aligned as required */
+    RECOIL_ERR_BUSY = -8,           /* serving: request refused by admission control */
+    RECOIL_ERR_NOT_FOUND = -9,
+};
+
+/* Device error word bits (set with atomic OR by the decode kernels). */
+enum {
+    RECOIL_DEVERR_UNDERFLOW = 1u,   /* a decode unit ran out of bitstream words */
+    RECOIL_DEVERR_BAD_ITEM = 2u,    /* batched decode: malformed work item */
+};
+
+typedef struct {
+    uint32_t lanes;         /* W: 32 or 64 for GPU decoding (1..64 accepted by the encoder) */
+    uint32_t quant_bits;    /* n: 1..16 accepted by the encoder; GPU decoding needs n <= 12 */
+    uint32_t symbol_bytes;  /* 1 (uint8) or 2 (uint16) */
+    uint32_t alphabet;      /* A: symbols lie in [0, A); A <= 256 for uint8, <= 65536 for uint16 */
+} recoil_config;
+
+typedef struct {
+    uint64_t n_symbols;      /* N */
+    uint64_t n_words;        /* B */
+    uint32_t splits;         /* M */
+    uint32_t lanes, quant_bits, symbol_bytes, alphabet;
+    uint64_t table_bytes;    /* packed frequency table */
+    uint64_t metadata_bytes; /* packed split metadata (Sec. 4.3) */
+    uint64_t total_bytes;    /* whole container: header + table + final states + metadata + words */
+} recoil_blob_info_t;
+
+typedef struct recoil_blob recoil_blob;   /* immutable encoded stream; safe to share between threads */
+typedef struct recoil_plan recoil_plan;   /* host-side decode plan for one blob on the GPU */
+
+const char *recoil_status_string(recoil_status s);
+const char *recoil_last_error(void);
+const char *recoil_version(void);
+
+/*
+ * Quantise symbol counts to a frequency table summing to 2^n (the paper builds
+ * static tables from symbol statistics, Sec. 5.1). Rule: f = max(1, floor(c 2^n / total))
+ * for present symbols, 0 otherwise; a shortfall is given out one unit per
+ * symbol in order of largest remainder (ties: smaller symbol); an excess is
+ * removed one unit at a time from the largest f > 1 (ties: smaller symbol).
+ * counts: host array of A uint64; f_out: host array of A uint32.
+ * Errors: INVALID_ARG, INFEASIBLE (no symbol present or more than 2^n present).
+ */
+recoil_status recoil_quantize(const uint64_t *counts, uint32_t alphabet, uint32_t quant_bits,
+                              uint32_t *f_out);
+
+/*
+ * Encode N symbols with one group of W interleaved rANS coders (Eq. 1 and the
+ * renormalisation of Eq. 3; words are appended in increasing lane order within
+ * each group, Sec. 2.2) and choose up to n_splits - 1 split points with the
+ * heuristic of Def. 4.1, recording for each the states and symbol indices
+ * found by the backward scan of Sec. 4.1.
+ *
+ * symbols: host array of N uint8 or uint16 (per cfg->symbol_bytes), each < A.
+ * freq:    host array of A uint32 summing to 2^n, or NULL to quantise the
+ *          symbol counts with recoil_quantize.
+ * n_splits: requested M >= 1. Fewer units are produced when the stream has
+ *          too few usable split points (e.g. N < W gives M = 1).
+ * out:     receives a new blob; free with recoil_blob_free.
+ * Serial on one host thread (Sec. 6 accepts a slow encoder). Not a hot path.
+ * Errors: INVALID_ARG, INFEASIBLE.
+ */
+recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
+                            const uint32_t *freq, uint32_t n_splits, recoil_blob **out);
+
+/*
+ * Decoder-adaptive combining (Sec. 3.3, end of Sec. 4.2): keep every
+ * ceil(M_in / target)-th split point, which leaves ceil(M_in / step) decode
+ * units (exactly `target` when it divides M_in), and re-express the stored
+ * differences against the new expectations. The bitstream is not touched.
+ * target >= M_in returns an equal copy. out: new blob.
+ * Errors: INVALID_ARG.
+ */
+recoil_status recoil_combine_splits(const recoil_blob *in, uint32_t target_splits, recoil_blob **out);
+
+/* Container bytes (layout above). Pass dst = NULL to query the size in *written.
+ * Errors: INVALID_ARG, BUFFER_TOO_SMALL. */
+recoil_status recoil_blob_serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *written);
+/* Parse and fully validate a container (header, table, every split point).
+ * Errors: INVALID_ARG, CORRUPT. */
+recoil_status recoil_blob_deserialize(const void *src, size_t len, recoil_blob **out);
+recoil_status recoil_blob_info(const recoil_blob *blob, recoil_blob_info_t *out);
+void recoil_blob_free(recoil_blob *blob);
+
+/*
+ * Plan a GPU decode of one blob. The plan unpacks the split metadata into a
+ * device-friendly layout and reports the device workspace it needs. The plan
+ * keeps its own reference to the blob's data; the blob may be freed first.
+ * device_bytes: receives the workspace size (bytes, 256-byte aligned sections).
+ * Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n > 12, N or B >= 2^32).
+ */
+recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, size_t *device_bytes);
+/* Copy bitstream, decode table and unpacked metadata into the caller-owned
+ * workspace d_workspace (device pointer, 256-byte aligned, >= device_bytes)
+ * with asynchronous copies on `stream`. Host sources stay owned by the plan.
+ * Errors: INVALID_ARG, ALIGNMENT, HIP. */
+recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, size_t bytes,
+                                 hipStream_t stream);
+/* Size in bytes of the split metadata as uploaded (part of device_bytes). */
+size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
+void recoil_plan_free(recoil_plan *plan);
+
+/*
+ * Decode on the GPU (Sec. 4.1: synchronisation, decoding and cross-boundary
+ * phases). Each decode unit runs on W lanes of a 64-lane wavefront (one unit
+ * per wave for W = 64, two for W = 32) and writes exactly the whole symbol
+ * groups it owns, so every output symbol is written once.
+ *
+ * d_workspace: the uploaded workspace (unchanged by decoding).
+ * d_out:       device buffer of N * symbol_bytes bytes, 16-byte aligned.
+ * d_error:     device uint32, zeroed by the caller; RECOIL_DEVERR_* bits are
+ *              OR-ed in if the data turn out to be corrupt (the kernels never
+ *              read or write outside the given buffers).
+ * Enqueues kernels on `stream` and returns; no allocation, no synchronisation,
+ * so the call can be captured in a HIP graph.
+ * Errors: INVALID_ARG, ALIGNMENT, HIP (launch failure).
+ */
+recoil_status recoil_decode(const recoil_plan *plan, const void *d_workspace, void *d_out,
+                            uint32_t *d_error, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECOIL_H */

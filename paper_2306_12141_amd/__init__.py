@@ -1,0 +1,176 @@
+"""librecoil: Recoil parallel rANS decoding on AMD MI355X (gfx950).
+
+Python surface over the C-ABI in include/recoil.h. Host arrays are numpy;
+device buffers are torch tensors on a ROCm device (used only for their memory
+and streams). Every decode runs in the HIP kernels of librecoil.so.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import RecoilError, check
+
+__all__ = ["Blob", "Plan", "encode", "quantize", "RecoilError", "version"]
+
+
+def version() -> str:
+    return _lib.recoil_version().decode()
+
+
+def _ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+def quantize(counts: np.ndarray, quant_bits: int) -> np.ndarray:
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    f = np.zeros(len(counts), dtype=np.uint32)
+    check(_lib.recoil_quantize(_ptr(counts), len(counts), quant_bits, _ptr(f)), "recoil_quantize")
+    return f
+
+
+class Blob:
+    """An encoded stream (bitstream + split metadata); immutable."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    def __del__(self, _free=_lib.recoil_blob_free):
+        h = getattr(self, "_h", None)
+        if h:
+            _free(h)
+            self._h = None
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    @property
+    def info(self) -> _lib.BlobInfo:
+        out = _lib.BlobInfo()
+        check(_lib.recoil_blob_info(self._h, C.byref(out)), "recoil_blob_info")
+        return out
+
+    @property
+    def splits(self) -> int:
+        return self.info.splits
+
+    @property
+    def dtype(self):
+        return np.uint8 if self.info.symbol_bytes == 1 else np.uint16
+
+    def combine(self, target_splits: int) -> "Blob":
+        h = C.c_void_p()
+        check(_lib.recoil_combine_splits(self._h, target_splits, C.byref(h)), "recoil_combine_splits")
+        return Blob(h)
+
+    def to_bytes(self) -> bytes:
+        n = C.c_size_t()
+        check(_lib.recoil_blob_serialize(self._h, None, 0, C.byref(n)), "recoil_blob_serialize")
+        buf = np.empty(n.value, dtype=np.uint8)
+        check(_lib.recoil_blob_serialize(self._h, _ptr(buf), n.value, C.byref(n)), "recoil_blob_serialize")
+        return buf.tobytes()
+
+    @staticmethod
+    def from_bytes(data: bytes) -> "Blob":
+        buf = np.frombuffer(data, dtype=np.uint8)
+        h = C.c_void_p()
+        check(_lib.recoil_blob_deserialize(_ptr(buf) if len(buf) else None, len(buf), C.byref(h)),
+              "recoil_blob_deserialize")
+        return Blob(h)
+
+
+def encode(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, splits: int = 1,
+           alphabet: Optional[int] = None, freq: Optional[np.ndarray] = None) -> Blob:
+    """Encode uint8/uint16 symbols into one interleaved stream with `splits` decode units."""
+    symbols = np.ascontiguousarray(symbols)
+    if symbols.dtype not in (np.uint8, np.uint16):
+        raise TypeError("symbols must be uint8 or uint16")
+    sb = symbols.dtype.itemsize
+    if alphabet is None:
+        alphabet = 256 if sb == 1 else 65536
+    cfg = _lib.Config(lanes, quant_bits, sb, alphabet)
+    fp = None
+    if freq is not None:
+        freq = np.ascontiguousarray(freq, dtype=np.uint32)
+        fp = _ptr(freq)
+    h = C.c_void_p()
+    check(_lib.recoil_encode(_ptr(symbols) if symbols.size else None, symbols.size, C.byref(cfg), fp,
+                             splits, C.byref(h)), "recoil_encode")
+    return Blob(h)
+
+
+def _stream_handle(stream) -> C.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Plan:
+    """GPU decode plan of one blob: device workspace layout plus decode launch."""
+
+    def __init__(self, blob: Blob):
+        self._h = C.c_void_p()
+        n = C.c_size_t()
+        check(_lib.recoil_plan_create(blob.handle, C.byref(self._h), C.byref(n)), "recoil_plan_create")
+        self.device_bytes = n.value
+        info = blob.info
+        self.n_symbols = info.n_symbols
+        self.symbol_bytes = info.symbol_bytes
+        self.splits = info.splits
+        self.lanes = info.lanes
+
+    def __del__(self, _free=_lib.recoil_plan_free):
+        h = getattr(self, "_h", None)
+        if h:
+            _free(h)
+            self._h = None
+
+    @property
+    def metadata_device_bytes(self) -> int:
+        return _lib.recoil_plan_metadata_device_bytes(self._h)
+
+    def allocate_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=device)
+
+    def upload(self, workspace, stream=None) -> None:
+        check(_lib.recoil_plan_upload(self._h, C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                      _stream_handle(stream)), "recoil_plan_upload")
+
+    def allocate_output(self, device="cuda"):
+        """A byte tensor of N * symbol_bytes bytes (torch has few uint16 kernels)."""
+        import torch
+        return torch.empty(max(self.n_symbols * self.symbol_bytes, 16), dtype=torch.uint8, device=device)
+
+    def symbols_of(self, out) -> np.ndarray:
+        """Host copy of the decoded symbols held in a byte tensor from allocate_output."""
+        host = out[: self.n_symbols * self.symbol_bytes].cpu().numpy()
+        return host.view(np.uint8 if self.symbol_bytes == 1 else np.uint16)
+
+    def decode(self, workspace, out, err, stream=None) -> None:
+        """Enqueue the decode kernels on `stream` (default: torch's current stream)."""
+        if out.numel() * out.element_size() < self.n_symbols * self.symbol_bytes:
+            raise ValueError("output tensor too small")
+        check(_lib.recoil_decode(self._h, C.c_void_p(workspace.data_ptr()), C.c_void_p(out.data_ptr()),
+                                 C.c_void_p(err.data_ptr()), _stream_handle(stream)), "recoil_decode")
+
+
+def decode_blob(blob: Blob, device="cuda"):
+    """Convenience: upload, decode and return (symbols tensor, error word)."""
+    import torch
+    plan = Plan(blob)
+    ws = plan.allocate_workspace(device)
+    plan.upload(ws)
+    out = plan.allocate_output(device)
+    err = torch.zeros(1, dtype=torch.int32, device=device)
+    plan.decode(ws, out, err)
+    torch.cuda.synchronize()
+    return plan.symbols_of(out), int(err.item())

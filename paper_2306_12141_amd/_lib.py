@@ -1,0 +1,73 @@
+"""ctypes binding of librecoil.so (argument marshalling only).
+
+Every decode step runs in the library's HIP kernels; this module converts
+numpy arrays and torch tensors into plain pointers and sizes. It raises at
+import time if the built library is missing: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "librecoil.so")
+
+if not os.path.exists(SO_PATH):
+    raise ImportError(
+        f"librecoil.so not found at {SO_PATH}; build it with `python -m paper_2306_12141_amd.build` "
+        "(hipcc, gfx950). There is no CPU fallback.")
+
+lib = C.CDLL(SO_PATH)
+
+P = C.c_void_p
+u32 = C.c_uint32
+u64 = C.c_uint64
+i32 = C.c_int32
+sz = C.c_size_t
+
+
+class Config(C.Structure):
+    _fields_ = [("lanes", u32), ("quant_bits", u32), ("symbol_bytes", u32), ("alphabet", u32)]
+
+
+class BlobInfo(C.Structure):
+    _fields_ = [("n_symbols", u64), ("n_words", u64), ("splits", u32), ("lanes", u32),
+                ("quant_bits", u32), ("symbol_bytes", u32), ("alphabet", u32),
+                ("table_bytes", u64), ("metadata_bytes", u64), ("total_bytes", u64)]
+
+
+def _sig(name, args, res=i32):
+    fn = getattr(lib, name)
+    fn.argtypes = args
+    fn.restype = res
+    return fn
+
+
+recoil_status_string = _sig("recoil_status_string", [i32], C.c_char_p)
+recoil_last_error = _sig("recoil_last_error", [], C.c_char_p)
+recoil_version = _sig("recoil_version", [], C.c_char_p)
+recoil_quantize = _sig("recoil_quantize", [P, u32, u32, P])
+recoil_encode = _sig("recoil_encode", [P, u64, C.POINTER(Config), P, u32, C.POINTER(P)])
+recoil_combine_splits = _sig("recoil_combine_splits", [P, u32, C.POINTER(P)])
+recoil_blob_serialize = _sig("recoil_blob_serialize", [P, P, sz, C.POINTER(sz)])
+recoil_blob_deserialize = _sig("recoil_blob_deserialize", [P, sz, C.POINTER(P)])
+recoil_blob_info = _sig("recoil_blob_info", [P, C.POINTER(BlobInfo)])
+recoil_blob_free = _sig("recoil_blob_free", [P], None)
+recoil_plan_create = _sig("recoil_plan_create", [P, C.POINTER(P), C.POINTER(sz)])
+recoil_plan_upload = _sig("recoil_plan_upload", [P, P, sz, P])
+recoil_plan_metadata_device_bytes = _sig("recoil_plan_metadata_device_bytes", [P], sz)
+recoil_plan_free = _sig("recoil_plan_free", [P], None)
+recoil_decode = _sig("recoil_decode", [P, P, P, P, P])
+
+
+class RecoilError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = recoil_last_error().decode(errors="replace")
+        super().__init__(f"{what}: {recoil_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, what: str) -> None:
+    if status != 0:
+        raise RecoilError(status, what)

@@ -1,0 +1,43 @@
+// Device-side layout shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace recoil {
+
+// Per decode unit (0-based u; unit u starts at split point u+1, the last unit
+// at the final states). Symbol groups are 0-based.
+struct UnitMeta {
+    uint32_t next;   // words available: the unit's first read is words[next - 1]
+    uint32_t top;    // first group decoded (the anchor; G-1 for the last unit)
+    uint32_t ghi;    // last group whose symbols this unit stores (inclusive, descending from here)
+    uint32_t glo;    // lowest group decoded and stored
+};
+
+// Per lane of a unit: recorded state (bits 0..15) and activation step
+// (bits 16..31) = top - group of the lane's recorded symbol. For the last unit
+// the word is the full 32-bit final state and every lane is active at once.
+//
+// Decode table entries, indexed by slot = x mod 2^n:
+//   8-bit symbols:  bits 0..7 symbol, 8..19 f(s), 20..31 slot - F(s)     (n <= 12, f < 4096)
+//   16-bit symbols: .x = f(s) | (slot - F(s)) << 16, .y = symbol
+struct DecodeParams {
+    const uint16_t *words;      // B words
+    const void *lut;            // 2^n entries
+    const UnitMeta *meta;       // M
+    const uint32_t *lanes;      // M x W
+    void *out;                  // N symbols
+    uint32_t *err;              // device error word
+    uint64_t n_symbols;
+    uint32_t units;
+    uint32_t quant_bits;
+    uint32_t fill_symbol;       // used when the table holds a single symbol (f = 2^n)
+    uint32_t single_symbol;     // nonzero: the stream is one repeated symbol
+};
+
+// Launchers (decode.hip). Return hipSuccess or the launch error.
+hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, hipStream_t stream);
+
+}  // namespace recoil

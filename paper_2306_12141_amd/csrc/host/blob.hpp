@@ -1,0 +1,60 @@
+// Internal host-side types of librecoil.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "recoil.h"
+
+namespace recoil {
+
+// Parameters fixed by the recommended set (Table "rANS parameters"): 32-bit
+// states, L = 2^16, 16-bit renormalisation words.
+constexpr uint32_t kLowerBits = 16;
+constexpr uint32_t kWordBits = 16;
+constexpr uint32_t kLower = 1u << kLowerBits;
+// The per-lane group distance to the anchor is stored in at most 16 bits (Sec. 4.3).
+constexpr uint64_t kMaxGroupDiff = 65535;
+
+// One encoded stream plus its split points, unpacked.
+struct BlobData {
+    uint32_t lanes = 0, quant_bits = 0, symbol_bytes = 0, alphabet = 0;
+    uint64_t n_symbols = 0;
+    std::vector<uint32_t> freq;          // f[s], sums to 2^n
+    std::vector<uint32_t> final_states;  // W
+    std::vector<uint16_t> words;         // B, written forward, read backward
+    // Split points k = 1..M-1 (index k-1), increasing word position.
+    std::vector<uint64_t> sp_next;       // p_k + 1: words available to the unit starting there
+    std::vector<uint64_t> sp_anchor;     // g_k: largest symbol group among the recorded lanes (0-based)
+    std::vector<uint16_t> sp_state;      // (M-1) x W recorded post-shift states (< 2^16, Lemma 3.1)
+    std::vector<uint16_t> sp_gdiff;      // (M-1) x W: g_k - group of lane j's recorded symbol
+    // Packed sections, computed once.
+    std::vector<uint8_t> table_bits;
+    std::vector<uint8_t> meta_bits;
+
+    uint32_t splits() const { return (uint32_t)sp_next.size() + 1; }
+    uint64_t groups() const { return (n_symbols + lanes - 1) / lanes; }
+    uint64_t n_words() const { return words.size(); }
+    uint64_t total_bytes() const {
+        return 48 + table_bits.size() + 4ull * lanes + meta_bits.size() + 2ull * words.size();
+    }
+    // Symbol index recorded for lane j at split point k (1-based k).
+    uint64_t split_index(uint32_t k, uint32_t j) const {
+        uint64_t g = sp_anchor[k - 1] - sp_gdiff[(uint64_t)(k - 1) * lanes + j];
+        return g * lanes + j;
+    }
+};
+
+// Fill table_bits / meta_bits; false if a value does not fit its series.
+bool pack_sections(BlobData &b);
+
+void set_error(const std::string &msg);
+recoil_status fail(recoil_status s, const std::string &msg);
+
+}  // namespace recoil
+
+struct recoil_blob {
+    std::shared_ptr<const recoil::BlobData> data;
+};

@@ -1,0 +1,175 @@
+// GPU decode planning: unpack split metadata into per-unit records, build the
+// slot -> (symbol, f, slot - F) decode table, lay out the device workspace and
+// launch the decode kernels.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "../device/decode.hpp"
+#include "blob.hpp"
+
+namespace recoil {
+
+namespace {
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
+
+struct PlanData {
+    std::shared_ptr<const BlobData> blob;
+    std::vector<UnitMeta> meta;          // M
+    std::vector<uint32_t> lanes;         // M x W
+    std::vector<uint8_t> lut;            // 2^n entries, 4 or 8 bytes each
+    bool single_symbol = false;
+    uint32_t fill_symbol = 0;
+    // Workspace layout (byte offsets from the workspace base).
+    size_t off_words = 0, off_lut = 0, off_meta = 0, off_lanes = 0, total = 0;
+};
+
+// Build the per-unit records of Sec. 4.1: unit u (0-based) starts at split
+// point u+1 or, for the last unit, at the final states; it decodes groups
+// top .. glo and stores ghi .. glo, where ghi is the group of its own
+// synchronisation completion point (all lanes switched on) and glo is one
+// above the previous unit's.
+recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
+    const BlobData &b = *bp;
+    const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
+    if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
+    if (n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs n <= 12");
+    if (b.n_symbols >= (1ull << 32) || b.n_words() >= (1ull << 32))
+        return fail(RECOIL_ERR_UNSUPPORTED, "plan: N and B must be below 2^32");
+    if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
+    pl.blob = bp;
+    const uint64_t G = b.groups();
+    pl.meta.resize(M);
+    pl.lanes.resize((size_t)M * W);
+    uint32_t prev_sync = 0;
+    for (uint32_t u = 0; u < M; ++u) {
+        UnitMeta &m = pl.meta[u];
+        m.glo = (u == 0) ? 0u : prev_sync + 1;
+        if (u + 1 == M) {
+            m.next = (uint32_t)b.n_words();
+            m.top = G ? (uint32_t)(G - 1) : 0u;
+            m.ghi = m.top;
+            for (uint32_t j = 0; j < W; ++j) pl.lanes[(size_t)u * W + j] = b.final_states[j];
+        } else {
+            const uint64_t k = u;   // split point u+1 is stored at index u
+            m.next = (uint32_t)b.sp_next[k];
+            m.top = (uint32_t)b.sp_anchor[k];
+            uint32_t maxdiff = 0;
+            for (uint32_t j = 0; j < W; ++j) {
+                const uint32_t d = b.sp_gdiff[k * W + j];
+                maxdiff = std::max(maxdiff, d);
+                pl.lanes[(size_t)u * W + j] = (uint32_t)b.sp_state[k * W + j] | (d << 16);
+            }
+            m.ghi = m.top - maxdiff;     // group where every lane has been switched on
+            prev_sync = m.ghi;
+        }
+    }
+    // Decode table.
+    const uint32_t slots = 1u << n;
+    uint32_t present = 0, only = 0;
+    for (uint32_t s = 0; s < b.alphabet; ++s)
+        if (b.freq[s]) { ++present; only = s; }
+    pl.single_symbol = present == 1;
+    pl.fill_symbol = only;
+    const size_t esz = b.symbol_bytes == 1 ? 4 : 8;
+    pl.lut.assign((size_t)slots * esz, 0);
+    uint32_t F = 0;
+    for (uint32_t s = 0; s < b.alphabet; ++s) {
+        const uint32_t f = b.freq[s];
+        for (uint32_t r = 0; r < f; ++r) {
+            const uint32_t slot = F + r;
+            if (b.symbol_bytes == 1) {
+                const uint32_t e = s | ((f & 0xFFFu) << 8) | (r << 20);
+                std::memcpy(&pl.lut[(size_t)slot * 4], &e, 4);
+            } else {
+                const uint32_t e0 = f | (r << 16), e1 = s;
+                std::memcpy(&pl.lut[(size_t)slot * 8], &e0, 4);
+                std::memcpy(&pl.lut[(size_t)slot * 8 + 4], &e1, 4);
+            }
+        }
+        F += f;
+    }
+    size_t off = 0;
+    pl.off_words = off; off = align_up(off + 2 * b.n_words() + 16);
+    pl.off_lut = off;   off = align_up(off + pl.lut.size());
+    pl.off_meta = off;  off = align_up(off + pl.meta.size() * sizeof(UnitMeta));
+    pl.off_lanes = off; off = align_up(off + pl.lanes.size() * 4);
+    pl.total = off;
+    return RECOIL_OK;
+}
+
+}  // namespace recoil
+
+struct recoil_plan {
+    recoil::PlanData d;
+};
+
+extern "C" {
+
+recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, size_t *device_bytes) {
+    using namespace recoil;
+    if (!blob || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_create: bad arguments");
+    *out = nullptr;
+    auto *p = new (std::nothrow) recoil_plan();
+    if (!p) return fail(RECOIL_ERR_INVALID_ARG, "plan_create: out of memory");
+    recoil_status st = build_plan(blob->data, p->d);
+    if (st) { delete p; return st; }
+    if (device_bytes) *device_bytes = p->d.total;
+    *out = p;
+    return RECOIL_OK;
+}
+
+size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan) {
+    if (!plan) return 0;
+    return plan->d.meta.size() * sizeof(recoil::UnitMeta) + plan->d.lanes.size() * 4;
+}
+
+recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t bytes, hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws) return fail(RECOIL_ERR_INVALID_ARG, "plan_upload: bad arguments");
+    const PlanData &pl = plan->d;
+    if (bytes < pl.total) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "plan_upload: workspace too small");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(RECOIL_ERR_ALIGNMENT, "plan_upload: workspace not 256-byte aligned");
+    char *base = static_cast<char *>(d_ws);
+    const BlobData &b = *pl.blob;
+    hipError_t e = hipSuccess;
+    if (b.n_words()) e = hipMemcpyAsync(base + pl.off_words, b.words.data(), 2 * b.n_words(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lut, pl.lut.data(), pl.lut.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_upload: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+void recoil_plan_free(recoil_plan *plan) { delete plan; }
+
+recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_out, uint32_t *d_error,
+                            hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws || !d_error || (!d_out && plan->d.blob->n_symbols))
+        return fail(RECOIL_ERR_INVALID_ARG, "decode: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(RECOIL_ERR_ALIGNMENT, "decode: output must be 16-byte and workspace 256-byte aligned");
+    const PlanData &pl = plan->d;
+    const BlobData &b = *pl.blob;
+    const char *base = static_cast<const char *>(d_ws);
+    DecodeParams p{};
+    p.words = reinterpret_cast<const uint16_t *>(base + pl.off_words);
+    p.lut = base + pl.off_lut;
+    p.meta = reinterpret_cast<const UnitMeta *>(base + pl.off_meta);
+    p.lanes = reinterpret_cast<const uint32_t *>(base + pl.off_lanes);
+    p.out = d_out;
+    p.err = d_error;
+    p.n_symbols = b.n_symbols;
+    p.units = b.splits();
+    p.quant_bits = b.quant_bits;
+    p.fill_symbol = pl.fill_symbol;
+    p.single_symbol = pl.single_symbol ? 1u : 0u;
+    hipError_t e = launch_decode(p, b.lanes, b.symbol_bytes, stream);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+}  // extern "C"

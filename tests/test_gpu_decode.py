@@ -1,0 +1,188 @@
+"""GPU parity: librecoil's HIP decoder against the seeded input symbols.
+
+Recoil is lossless, so the expected output of a decode is the symbol sequence
+that was encoded (drawn by the seeded generators in `synth`). Containers come
+either from librecoil's encoder (checked byte-identical to the oracle's in the
+CPU tests) or directly from the oracle (arbitrary split sets). Every output is
+compared element by element, bit-exact; the output buffer is pre-filled with
+two different patterns so that a symbol left unwritten is caught.
+"""
+
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_12141_amd as m
+    return m
+
+
+def gpu_decode(rc, blob, poison=(0xA5, 0x5A)):
+    """Decode twice, into buffers pre-filled with two patterns; both must agree."""
+    plan = rc.Plan(blob)
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    outs = []
+    for pv in poison:
+        out = plan.allocate_output()
+        out.fill_(pv)
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        plan.decode(ws, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        outs.append(plan.symbols_of(out))
+    assert np.array_equal(outs[0], outs[1]), "some symbols were not written"
+    return outs[0]
+
+
+def _syms(seed, n, A, dtype=np.uint8, skew=None):
+    if skew is None:
+        return (synth.splitmix64(seed, 0, n) % np.uint64(A)).astype(dtype)
+    return synth.draw_symbols(synth.zipf_pmf(A, skew), seed, n, dtype)
+
+
+def test_c0_laplace_1mib(rc, orc):
+    spec = synth.c0_spec()
+    s = spec.generate()
+    _say("case c0", spec)
+    blob = rc.encode(s, lanes=32, quant_bits=11, splits=256)
+    assert blob.splits == 256
+    out = gpu_decode(rc, blob)
+    assert np.array_equal(out, s)
+
+
+@pytest.mark.parametrize("target", [128, 100, 17, 2, 1])
+def test_c0_combined(rc, target):
+    spec = synth.c0_spec()
+    s = spec.generate()
+    _say("case c0 combined", target)
+    blob = rc.encode(s, lanes=32, quant_bits=11, splits=256).combine(target)
+    assert np.array_equal(gpu_decode(rc, blob), s)
+
+
+CASES = [
+    # (lanes, n, symbol dtype, alphabet, N, splits, zipf exponent or None)
+    (32, 11, np.uint8, 256, 100_000, 37, 1.1),
+    (64, 11, np.uint8, 256, 100_000, 37, 1.1),
+    (32, 12, np.uint8, 256, 300_001, 64, 0.8),
+    (64, 12, np.uint8, 256, 300_001, 64, 1.5),
+    (32, 10, np.uint8, 200, 77_777, 9, None),
+    (32, 12, np.uint16, 4096, 120_003, 20, 1.0),
+    (64, 12, np.uint16, 4096, 120_003, 20, 1.3),
+    (32, 12, np.uint16, 4096, 50_000, 5, None),
+    (32, 8, np.uint8, 3, 40_000, 30, 2.5),
+    (64, 8, np.uint8, 2, 40_000, 30, 3.0),
+    (32, 11, np.uint8, 256, 31, 4, None),       # N < W: one unit
+    (64, 11, np.uint8, 256, 65, 4, None),       # partial last group
+    (32, 11, np.uint8, 256, 1, 1, None),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)), ids=[f"W{c[0]}_n{c[1]}_{np.dtype(c[2]).name}_N{c[4]}_M{c[5]}" for c in CASES])
+def test_streams(rc, ci):
+    W, n, dt, A, N, M, z = CASES[ci]
+    _say("case", CASES[ci])
+    s = _syms(1000 + ci, N, A, dt, z)
+    blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
+    assert np.array_equal(gpu_decode(rc, blob), s)
+
+
+def test_single_symbol_stream(rc):
+    s = np.full(10_000, 7, dtype=np.uint8)
+    for n in (8, 12):
+        blob = rc.encode(s, lanes=32, quant_bits=n, splits=4)
+        assert np.array_equal(gpu_decode(rc, blob), s)
+
+
+def test_empty_stream(rc):
+    s = np.zeros(0, dtype=np.uint8)
+    blob = rc.encode(s, lanes=32, quant_bits=8, splits=1)
+    assert gpu_decode(rc, blob).size == 0
+
+
+@pytest.mark.parametrize("W", [32, 64])
+def test_every_single_split_point(rc, orc, W):
+    """Every usable split word of a small stream as a lone split (oracle-built containers)."""
+    from tests import _fmt
+    N = 40 * W + 5
+    s = _syms(3 + W, N, 4, np.uint8, 1.2)
+    p = orc.params(lanes=W, quant_bits=10, alphabet=4)
+    f = orc.quantize(np.bincount(s, minlength=4).astype(np.uint64), 10)
+    enc = orc.encode(s, p, 1, freq=f)
+    hdr = _fmt.parse(enc.container())
+    n_cand = 0
+    for k in range(hdr["B"]):
+        cand = enc.candidate_at(k)
+        if cand is None:
+            continue
+        n_cand += 1
+        c = orc.assemble(p, N, f, hdr["words"], hdr["final"], [cand.pos], cand.states[None, :],
+                         cand.indices[None, :])
+        blob = rc.Blob.from_bytes(c)
+        assert np.array_equal(gpu_decode(rc, blob), s), k
+    assert n_cand > 0
+
+
+def test_random_split_sets(rc, orc):
+    from tests import _fmt
+    W, N = 32, 20_000
+    s = _syms(99, N, 256, np.uint8, 1.1)
+    p = orc.params(lanes=W, quant_bits=11)
+    f = orc.quantize(np.bincount(s, minlength=256).astype(np.uint64), 11)
+    enc = orc.encode(s, p, 1, freq=f)
+    hdr = _fmt.parse(enc.container())
+    rng = np.random.default_rng(5)
+    cands = []
+    for k in rng.choice(hdr["B"], size=400, replace=False):
+        c = enc.candidate_at(int(k))
+        if c is not None:
+            cands.append(c)
+    cands.sort(key=lambda c: c.pos)
+    for trial in range(6):
+        pick = sorted(rng.choice(len(cands), size=min(len(cands), 3 + 9 * trial), replace=False))
+        chosen = [cands[i] for i in pick]
+        # Synchronisation points must be monotone (the container validator enforces it).
+        chosen = [c for i, c in enumerate(chosen) if all(c.imin >= d.imin for d in chosen[:i])]
+        cont = orc.assemble(p, N, f, hdr["words"], hdr["final"], [c.pos for c in chosen],
+                            np.stack([c.states for c in chosen]), np.stack([c.indices for c in chosen]))
+        assert np.array_equal(gpu_decode(rc, rc.Blob.from_bytes(cont)), s)
+
+
+def test_corrupt_offset_sets_error_word(rc, orc):
+    """A container that passes host validation but makes unit 0 run out of words."""
+    from tests import _fmt
+    W, N = 32, 4000
+    s = _syms(17, N, 256, np.uint8, 1.1)
+    p = orc.params(lanes=W, quant_bits=11)
+    f = orc.quantize(np.bincount(s, minlength=256).astype(np.uint64), 11)
+    enc = orc.encode(s, p, 1, freq=f)
+    hdr = _fmt.parse(enc.container())
+    cand = next(c for c in (enc.candidate_at(k) for k in range(hdr["B"] - 1, 0, -1)) if c is not None)
+    # Claim the split word is word 0: the unit starts with one word and needs many.
+    cont = orc.assemble(p, N, f, hdr["words"], hdr["final"], [0], cand.states[None, :], cand.indices[None, :])
+    blob = rc.Blob.from_bytes(cont)
+    plan = rc.Plan(blob)
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) & 1

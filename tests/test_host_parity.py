@@ -1,0 +1,130 @@
+"""Host-side parity: librecoil's encoder, container writer and combiner produce
+exactly the oracle's bytes on seeded inputs, and its validator rejects
+corrupted containers. Runs on the CPU (no kernel launches)."""
+
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def rc():
+    import paper_2306_12141_amd as m
+    return m
+
+
+def _syms(seed, n, A, dtype=np.uint8, skew=None):
+    if skew is None:
+        return (synth.splitmix64(seed, 0, n) % np.uint64(A)).astype(dtype)
+    return synth.draw_symbols(synth.zipf_pmf(A, skew), seed, n, dtype)
+
+
+CASES = [
+    # lanes, n, dtype, alphabet, N, splits, zipf
+    (32, 11, np.uint8, 256, 200_000, 50, 1.1),
+    (64, 12, np.uint8, 256, 200_000, 50, 0.9),
+    (1, 8, np.uint8, 16, 5_000, 12, 1.0),
+    (3, 10, np.uint8, 100, 20_000, 17, None),
+    (17, 16, np.uint8, 256, 50_000, 9, 1.4),
+    (32, 12, np.uint16, 4096, 100_000, 20, 1.2),
+    (32, 16, np.uint16, 60000, 80_000, 8, None),
+    (32, 11, np.uint8, 256, 10, 4, None),
+    (32, 11, np.uint8, 256, 0, 1, None),
+    (32, 12, np.uint8, 2, 100_000, 100, 4.0),
+    (64, 4, np.uint8, 3, 30_000, 1000, 0.5),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_encode_byte_identical(rc, orc, ci):
+    W, n, dt, A, N, M, z = CASES[ci]
+    s = _syms(2000 + ci, N, A, dt, z)
+    mine = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A).to_bytes()
+    ref = orc.encode(s, orc.params(lanes=W, quant_bits=n, symbol_bytes=dt().itemsize, alphabet=A), M).container()
+    assert mine == ref
+
+
+def test_c0_identical_and_combines(rc, orc):
+    spec = synth.c0_spec()
+    s = spec.generate()
+    blob = rc.encode(s, lanes=32, quant_bits=11, splits=256)
+    ref = orc.encode(s, orc.params(lanes=32, quant_bits=11), 256).container()
+    assert blob.to_bytes() == ref
+    for t in (255, 128, 77, 16, 3, 1, 1000):
+        assert blob.combine(t).to_bytes() == orc.combine(ref, t)
+    info = blob.info
+    assert info.splits == 256 and info.total_bytes == len(ref)
+
+
+def test_given_frequency_table(rc, orc):
+    s = _syms(5, 30_000, 8)
+    f = np.array([100, 200, 300, 400, 500, 300, 200, 48], dtype=np.uint32)
+    assert f.sum() == 2048
+    mine = rc.encode(s, lanes=32, quant_bits=11, splits=10, alphabet=8, freq=f).to_bytes()
+    ref = orc.encode(s, orc.params(lanes=32, quant_bits=11, alphabet=8), 10, freq=f).container()
+    assert mine == ref
+
+
+def test_quantize_matches_oracle(rc, orc):
+    for seed in range(20):
+        A = 1 + seed * 13
+        counts = (synth.splitmix64(seed, 0, A) % np.uint64(1000)).astype(np.uint64)
+        counts[::3] = 0
+        if counts.sum() == 0:
+            continue
+        for n in (8, 12, 16):
+            if np.count_nonzero(counts) > (1 << n):
+                continue
+            assert np.array_equal(rc.quantize(counts, n), orc.quantize(counts, n))
+
+
+def test_deserialize_roundtrip(rc):
+    s = _syms(1, 50_000, 256, np.uint8, 1.1)
+    data = rc.encode(s, lanes=32, quant_bits=11, splits=20).to_bytes()
+    assert rc.Blob.from_bytes(data).to_bytes() == data
+
+
+def test_corruption_rejected(rc):
+    s = _syms(2, 50_000, 256, np.uint8, 1.1)
+    data = bytearray(rc.encode(s, lanes=32, quant_bits=11, splits=20).to_bytes())
+    bad = [data[:47], data[:-1], data + b"\0"]
+    for off in (0, 4, 6, 7, 8, 9, 12, 24, 32, 36, 40):
+        d = bytearray(data)
+        d[off] ^= 0xFF
+        bad.append(d)
+    for d in bad:
+        with pytest.raises(rc.RecoilError):
+            rc.Blob.from_bytes(bytes(d))
+    # Flip bits inside the metadata: must be rejected or still decode to a valid layout.
+    hdr_meta = int.from_bytes(data[40:44], "little")
+    tb = int.from_bytes(data[36:40], "little")
+    start = 48 + tb + 4 * 32
+    rejected = 0
+    for k in range(0, hdr_meta, max(1, hdr_meta // 64)):
+        d = bytearray(data)
+        d[start + k] ^= 0x80
+        try:
+            rc.Blob.from_bytes(bytes(d))
+        except rc.RecoilError:
+            rejected += 1
+    assert rejected > 0
+
+
+def test_invalid_arguments(rc):
+    with pytest.raises(rc.RecoilError):
+        rc.encode(np.array([300], dtype=np.uint16), lanes=32, quant_bits=11, alphabet=256)
+    with pytest.raises(rc.RecoilError):
+        rc.encode(np.arange(10, dtype=np.uint8), lanes=0, quant_bits=11)
+    with pytest.raises(rc.RecoilError):
+        rc.encode(np.arange(10, dtype=np.uint8), lanes=32, quant_bits=3)   # 10 symbols > 8 slots
+
+
+def test_plan_rejects_unsupported(rc):
+    s = _syms(3, 10_000, 256)
+    with pytest.raises(rc.RecoilError):
+        rc.Plan(rc.encode(s, lanes=16, quant_bits=11, splits=4))
+    with pytest.raises(rc.RecoilError):
+        rc.Plan(rc.encode(s, lanes=32, quant_bits=13, splits=4))
+    plan = rc.Plan(rc.encode(s, lanes=32, quant_bits=11, splits=4))
+    assert plan.device_bytes > 0 and plan.splits == 4
