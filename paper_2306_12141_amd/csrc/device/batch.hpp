@@ -1,0 +1,55 @@
+// Device-side layout of a batched decode (many independent streams, one launch).
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "decode.hpp"
+
+namespace recoil {
+
+// One stream of the batch. Offsets are bytes from the workspace base (words,
+// table, unit records, lane records) or from the output base (out).
+struct StreamDesc {
+    uint64_t words_off, lut_off, meta_off, lanes_off, out_off;
+    uint64_t n_symbols;
+    uint32_t units;
+    uint8_t quant_bits, symbol_bytes, lanes, single_symbol;
+    uint32_t fill_symbol;
+    uint32_t pad;
+};
+static_assert(sizeof(StreamDesc) == 64, "StreamDesc is 64 bytes");
+
+// A run of consecutive unit pairs (W = 32) or units (W = 64) of one stream,
+// decoded by one workgroup.
+struct WorkItem {
+    uint32_t stream;
+    uint32_t first;     // first pair (W = 32) or unit (W = 64)
+    uint32_t count;
+    uint32_t pad;
+};
+
+struct BatchParams {
+    const unsigned char *ws;      // workspace base
+    unsigned char *out;           // output base
+    const StreamDesc *streams;
+    const WorkItem *items;
+    uint32_t *head;               // work-queue head (device counter, reset before each launch)
+    uint32_t *err;
+    uint32_t n_items;
+    uint32_t lut_bytes;           // LDS bytes reserved for the largest table in the batch
+};
+
+struct BatchTuning {
+    uint32_t waves;       // waves per workgroup: 8 or 16
+    uint32_t chunk_groups;// K: groups per super-step (ring chunk = K*W words): 4 or 8
+    uint32_t blocks_per_cu;// 0: occupancy limit
+};
+
+// Persistent batched launch: queue-head reset kernel + decode kernel on `stream`.
+hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t stream);
+// Occupancy-derived workgroups per CU for a tuning (0 if the tuning is not available).
+int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes);
+
+}  // namespace recoil

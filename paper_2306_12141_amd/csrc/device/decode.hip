@@ -1,125 +1,61 @@
 // Recoil split decoding on gfx950 (Lin et al., ICPP 2023, Sec. 4.1).
 //
-// Mapping: a decode unit is W interleaved rANS lanes; a 64-lane wavefront runs
-// one unit (W = 64) or two (W = 32, one per half-wave). Lane j of a unit holds
-// coder j's state in a VGPR. Per symbol group, going downwards:
-//   read step   lanes whose state fell below L read one 16-bit word each, in
-//               decreasing lane order (Sec. 2.2, Eq. 4); the per-lane offset is
-//               the count of reading lanes above it in the unit, taken from a
-//               ballot and a masked bit count;
-//   decode step slot = x mod 2^n indexes the decode table in LDS, giving the
-//               symbol, f and slot - F; x <- f (x >> n) + slot - F (Eq. 2).
-// Synchronisation (Sec. 4.1.1): lane j is switched on, with its recorded 16-bit
-// state, at the read step of the group its recorded symbol belongs to, i.e.
-// just before its first read; symbols of groups above the unit's own range are
-// decoded only to advance the states and are not stored. The unit stores
-// groups ghi .. glo (its decoding and cross-boundary phases), so every output
-// symbol is written by exactly one unit.
-#include "decode.hpp"
+// Mapping. A decode unit is W interleaved rANS lanes; one 64-lane wavefront
+// runs one unit (W = 64) or two (W = 32, one per half-wave). Lane j of a unit
+// keeps coder j's 32-bit state in a VGPR. The kernel is persistent: each
+// workgroup stages the slot -> (symbol, f, slot - F) table in LDS once and its
+// waves then walk over unit pairs.
+//
+// Per symbol group, going downwards (Sec. 2.2: the decoder consumes words in
+// decreasing lane order before decoding a group):
+//   read step   lanes with x < L take one 16-bit word each (Eq. 4). The lane's
+//               word is the (count of reading lanes below it)-th of the words
+//               the group consumes, a ballot plus mbcnt; words come from a
+//               per-unit ring in LDS, so the dependent chain per group has two
+//               LDS round trips and no global-memory latency;
+//   decode step slot = x mod 2^n indexes the LDS table; x <- f (x >> n) + slot - F (Eq. 2);
+//               the symbol is stored directly (64 consecutive bytes per wave).
+// Bitstream ring. Words are fetched in chunks of C = K*W words, the most a unit
+// can consume in K groups (at most one word per symbol, since b >= n). A chunk
+// is requested into registers at the start of a K-group super-step whenever
+// fewer than 2C words remain resident, and written to the ring at its end, so
+// the global-memory latency overlaps K groups of decoding. The ring holds
+// 3C words plus a 64-word mirror of its first 64 slots, so a group's reads
+// never wrap inside a wave.
+// Synchronisation (Sec. 4.1.1). Lane j is switched on, with its recorded
+// 16-bit state, at the read step of the group its recorded symbol belongs to,
+// just before its first read. Groups above the unit's own range are decoded
+// only to advance the states. The unit stores groups ghi .. glo (decoding and
+// cross-boundary phases), so each output symbol is written by exactly one unit.
+// Super-steps that contain synchronisation, the partial last group or the end
+// of a unit run a predicated body; all others run the unpredicated one.
+#include <algorithm>
+
+#include "decode_core.hpp"
 
 namespace recoil {
 
 namespace {
 
-constexpr uint32_t kL = 1u << 16;
-constexpr int kWaves = 4;                 // waves per workgroup
-constexpr int kBlock = kWaves * 64;
+using namespace dev;
 
-template <typename Sym>
-struct Table;
-
-template <>
-struct Table<uint8_t> {
-    using Entry = uint32_t;
-    __device__ static inline uint32_t step(const Entry *lut, uint32_t &x, uint32_t n, uint32_t mask) {
-        const Entry e = lut[x & mask];
-        const uint32_t f = (e >> 8) & 0xFFFu;
-        const uint32_t off = e >> 20;
-        x = f * (x >> n) + off;
-        return e & 0xFFu;
-    }
-};
-
-template <>
-struct Table<uint16_t> {
-    using Entry = uint2;
-    __device__ static inline uint32_t step(const Entry *lut, uint32_t &x, uint32_t n, uint32_t mask) {
-        const Entry e = lut[x & mask];
-        const uint32_t f = e.x & 0xFFFFu;
-        const uint32_t off = e.x >> 16;
-        x = f * (x >> n) + off;
-        return e.y;
-    }
-};
-
-template <int W, typename Sym>
-__global__ __launch_bounds__(kBlock) void decode_units(DecodeParams p) {
-    using T = Table<Sym>;
-    using Entry = typename T::Entry;
+template <int W, typename Sym, int K, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void decode_units(DecodeParams p) {
+    using D = PairDecoder<W, Sym, K, WAVES>;
+    using G = Geo<W, Sym, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
-    Entry *lut = reinterpret_cast<Entry *>(smem);
-    const uint32_t n = p.quant_bits;
-    const uint32_t mask = (1u << n) - 1u;
+    typename D::Entry *lut = reinterpret_cast<typename D::Entry *>(smem + G::RINGS);
     {
-        const Entry *src = static_cast<const Entry *>(p.lut);
-        for (uint32_t i = threadIdx.x; i <= mask; i += kBlock) lut[i] = src[i];
+        const auto *src = static_cast<const typename D::Entry *>(p.lut);
+        const uint32_t slots = 1u << p.quant_bits;
+        for (uint32_t i = threadIdx.x; i < slots; i += 64 * WAVES) lut[i] = src[i];
     }
     __syncthreads();
-
-    constexpr uint32_t S = 64 / W;   // units per wave
+    const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t j = lane % W;
-    const uint32_t unit = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * S + lane / W;
-    const bool valid = unit < p.units;
-    UnitMeta m = {0, 0, 0, 1};
-    uint32_t rec = 0;
-    if (valid) {
-        m = p.meta[unit];
-        rec = p.lanes[(uint64_t)unit * W + j];
-    }
-    const bool is_last = valid && unit + 1 == p.units;
-    uint32_t x = is_last ? rec : 0u;
-    bool active = is_last;
-    const uint32_t act = is_last ? 0u : (rec >> 16);
-    uint32_t steps = (valid && m.top + 1 > m.glo) ? m.top + 1 - m.glo : 0u;
-    uint32_t next = m.next;
-    Sym *out = static_cast<Sym *>(p.out);
-
-    for (uint32_t k = 0;; ++k) {
-        bool live = k < steps;
-        if (!__any(live)) break;
-        // Read step before group h (Sec. 4.1.1: activation happens right before a lane's first read).
-        if (live && !active && k == act) {
-            active = true;
-            x = rec & 0xFFFFu;
-        }
-        const bool need = live && active && x < kL;
-        const uint64_t ballot = __ballot(need);
-        uint32_t cnt, below;
-        if (W == 64) {
-            cnt = (uint32_t)__popcll(ballot);
-            below = (uint32_t)__popcll(ballot & ((1ull << lane) - 1ull));
-        } else {
-            const uint32_t hm = (uint32_t)(ballot >> (lane & 32u));
-            cnt = (uint32_t)__popc(hm);
-            below = (uint32_t)__popc(hm & ((1u << j) - 1u));
-        }
-        if (live && cnt > next) {
-            // Corrupt metadata: the unit would read below the start of the bitstream.
-            if (j == 0) atomicOr(p.err, 1u);
-            steps = k;
-            continue;
-        }
-        if (need) x = (x << 16) | p.words[next - cnt + below];
-        next -= live ? cnt : 0u;
-        // Decode group h (Eq. 2).
-        const uint32_t h = m.top - k;
-        const uint64_t i = (uint64_t)h * W + j;
-        if (live && active && i < p.n_symbols) {
-            const uint32_t s = T::step(lut, x, n, mask);
-            if (h <= m.ghi) out[i] = (Sym)s;
-        }
-    }
+    const uint32_t npairs = (p.units + G::S - 1) / G::S;
+    D d(p, smem, lut, wave * G::WAVE_LDS, lane);
+    for (uint32_t pair = blockIdx.x * WAVES + wave; pair < npairs; pair += gridDim.x * WAVES) d.run(pair);
 }
 
 template <typename Sym>
@@ -127,12 +63,24 @@ __global__ __launch_bounds__(256) void fill_symbol(Sym *out, uint64_t n, Sym v) 
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) out[i] = v;
 }
 
-template <int W, typename Sym>
+template <int W, typename Sym, int K, int WAVES>
 hipError_t launch_units(const DecodeParams &p, hipStream_t stream) {
-    const uint32_t per_block = kWaves * (64 / W);
-    const uint32_t blocks = (p.units + per_block - 1) / per_block;
-    const size_t lds = (size_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits;
-    hipLaunchKernelGGL((decode_units<W, Sym>), dim3(blocks), dim3(kBlock), lds, stream, p);
+    using G = Geo<W, Sym, K, WAVES>;
+    const size_t lds = G::RINGS + ((size_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits);
+    static int per_cu = -1, cus = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES>, 64 * WAVES,
+                                                         G::RINGS + ((size_t)sizeof(typename Table<Sym>::Entry) << 12)) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+    }
+    const uint32_t pairs = (p.units + G::S - 1) / G::S;
+    const uint32_t need = (pairs + WAVES - 1) / WAVES;
+    const uint32_t blocks = std::min<uint32_t>(need, (uint32_t)(cus * per_cu));
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(std::max(blocks, 1u)), dim3(64 * WAVES), lds, stream, p);
     return hipGetLastError();
 }
 
@@ -150,10 +98,10 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
     }
-    if (lanes == 32 && symbol_bytes == 1) return launch_units<32, uint8_t>(p, stream);
-    if (lanes == 64 && symbol_bytes == 1) return launch_units<64, uint8_t>(p, stream);
-    if (lanes == 32 && symbol_bytes == 2) return launch_units<32, uint16_t>(p, stream);
-    if (lanes == 64 && symbol_bytes == 2) return launch_units<64, uint16_t>(p, stream);
+    if (lanes == 32 && symbol_bytes == 1) return launch_units<32, uint8_t, 8, 16>(p, stream);
+    if (lanes == 64 && symbol_bytes == 1) return launch_units<64, uint8_t, 8, 16>(p, stream);
+    if (lanes == 32 && symbol_bytes == 2) return launch_units<32, uint16_t, 4, 16>(p, stream);
+    if (lanes == 64 && symbol_bytes == 2) return launch_units<64, uint16_t, 4, 16>(p, stream);
     return hipErrorInvalidValue;
 }
 

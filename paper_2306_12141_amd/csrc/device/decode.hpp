@@ -12,7 +12,7 @@ namespace recoil {
 struct UnitMeta {
     uint32_t next;   // words available: the unit's first read is words[next - 1]
     uint32_t top;    // first group decoded (the anchor; G-1 for the last unit)
-    uint32_t ghi;    // last group whose symbols this unit stores (inclusive, descending from here)
+    uint32_t ghi;    // highest group whose symbols this unit stores
     uint32_t glo;    // lowest group decoded and stored
 };
 
@@ -23,8 +23,13 @@ struct UnitMeta {
 // Decode table entries, indexed by slot = x mod 2^n:
 //   8-bit symbols:  bits 0..7 symbol, 8..19 f(s), 20..31 slot - F(s)     (n <= 12, f < 4096)
 //   16-bit symbols: .x = f(s) | (slot - F(s)) << 16, .y = symbol
+//
+// The words array handed to the kernels is readable (padding) up to the next
+// multiple of kChunkPadWords past B, because bitstream chunks are fetched whole.
+constexpr uint32_t kChunkPadWords = 1024;
+
 struct DecodeParams {
-    const uint16_t *words;      // B words
+    const uint16_t *words;      // B words (+ padding, see above)
     const void *lut;            // 2^n entries
     const UnitMeta *meta;       // M
     const uint32_t *lanes;      // M x W

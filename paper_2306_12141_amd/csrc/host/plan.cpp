@@ -5,26 +5,14 @@
 #include <cstring>
 #include <new>
 
-#include "../device/decode.hpp"
-#include "blob.hpp"
+#include "plan.hpp"
 
 namespace recoil {
 
 namespace {
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kAlign = kWsAlign;
+inline size_t align_up(size_t v) { return ws_align(v); }
 }  // namespace
-
-struct PlanData {
-    std::shared_ptr<const BlobData> blob;
-    std::vector<UnitMeta> meta;          // M
-    std::vector<uint32_t> lanes;         // M x W
-    std::vector<uint8_t> lut;            // 2^n entries, 4 or 8 bytes each
-    bool single_symbol = false;
-    uint32_t fill_symbol = 0;
-    // Workspace layout (byte offsets from the workspace base).
-    size_t off_words = 0, off_lut = 0, off_meta = 0, off_lanes = 0, total = 0;
-};
 
 // Build the per-unit records of Sec. 4.1: unit u (0-based) starts at split
 // point u+1 or, for the last unit, at the final states; it decodes groups
@@ -92,7 +80,7 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl
         F += f;
     }
     size_t off = 0;
-    pl.off_words = off; off = align_up(off + 2 * b.n_words() + 16);
+    pl.off_words = off; off += words_section_bytes(b.n_words());
     pl.off_lut = off;   off = align_up(off + pl.lut.size());
     pl.off_meta = off;  off = align_up(off + pl.meta.size() * sizeof(UnitMeta));
     pl.off_lanes = off; off = align_up(off + pl.lanes.size() * 4);

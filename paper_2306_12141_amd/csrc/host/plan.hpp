@@ -1,0 +1,33 @@
+// Host-side GPU decode plan of one stream (shared by single-stream, batched
+// and serving paths).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "../device/decode.hpp"
+#include "blob.hpp"
+
+namespace recoil {
+
+struct PlanData {
+    std::shared_ptr<const BlobData> blob;
+    std::vector<UnitMeta> meta;          // M
+    std::vector<uint32_t> lanes;         // M x W
+    std::vector<uint8_t> lut;            // 2^n entries, 4 or 8 bytes each
+    bool single_symbol = false;
+    uint32_t fill_symbol = 0;
+    // Workspace layout of a single-stream plan (byte offsets from the workspace base).
+    size_t off_words = 0, off_lut = 0, off_meta = 0, off_lanes = 0, total = 0;
+};
+
+constexpr size_t kWsAlign = 256;
+inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// Unpack split metadata and build the decode table; fills the single-stream layout.
+recoil_status build_plan(const std::shared_ptr<const BlobData> &blob, PlanData &plan);
+
+// Bytes of the words section for B words (padded so chunks can be fetched whole).
+inline size_t words_section_bytes(uint64_t n_words) { return ws_align(2 * (n_words + kChunkPadWords)); }
+
+}  // namespace recoil
