@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the W=64 and combined-split runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="symbols in the oracle's sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run a plain device copy of BYTES (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build decodes on a single MI355X "
@@ -195,6 +197,15 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
+        # the decode kernel's counters to bytes.
+        src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     base = run_c1(args, torch, np, rc, synth)
     extras = {}
     if not args.no_extras:

@@ -97,6 +97,17 @@ typedef struct {
     uint64_t total_bytes;    /* whole container: header + table + final states + metadata + words */
 } recoil_blob_info_t;
 
+/* Launch shape of the decode kernels.
+ *   waves          waves per workgroup (8 or 16); the waves of a workgroup share one
+ *                  decode table in LDS
+ *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
+ *                  ring holds 4 K W words (3 K W ring + K W mirror). K = 8 needs waves = 8
+ *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)
+ *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit) */
+typedef struct {
+    uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu;
+} recoil_tuning;
+
 typedef struct recoil_blob recoil_blob;   /* immutable encoded stream; safe to share between threads */
 typedef struct recoil_plan recoil_plan;   /* host-side decode plan for one blob on the GPU */
 
@@ -170,6 +181,9 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, siz
                                  hipStream_t stream);
 /* Size in bytes of the split metadata as uploaded (part of device_bytes). */
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
+/* Launch shape used by recoil_decode for this plan (default 16 waves, K = 4).
+ * Errors: INVALID_ARG (unsupported shape). */
+recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *tuning);
 void recoil_plan_free(recoil_plan *plan);
 
 /*

@@ -17,19 +17,6 @@
 extern "C" {
 #endif
 
-/* Launch shape of the batched kernel.
- *   waves          waves per workgroup (8 or 16); all waves of a workgroup share one
- *                  decode table in LDS, so this also sets how many tables a CU holds
- *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
- *                  ring holds 3 K W words, so K trades LDS (occupancy) against overhead
- *   pairs_per_wave work-item size in unit pairs per wave (1..64): one item is
- *                  waves * pairs_per_wave pairs of one stream, the table is restaged
- *                  only between items of different streams
- *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit) */
-typedef struct {
-    uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu;
-} recoil_tuning;
-
 typedef struct recoil_batch recoil_batch;
 typedef struct recoil_graph recoil_graph;
 

@@ -4,7 +4,7 @@
 // Host planning cuts every stream into work items (runs of consecutive unit
 // pairs of one stream) and orders them largest stream first. Each persistent
 // workgroup pops an item from a device counter, restages the decode table in
-// LDS only when the item belongs to a different stream than the previous one,
+// LDS only when the item belongs to a different stream than its previous item,
 // and its waves decode the item's pairs with the same per-pair decoder as the
 // single-stream kernel. The queue head lives in device memory and is reset by
 // a one-thread kernel launched just before, so the pair of launches can be
@@ -20,42 +20,34 @@ namespace {
 
 using namespace dev;
 
-template <int K, int WAVES>
-struct BatchGeo {
-    static constexpr uint32_t A = Geo<32, uint8_t, K, WAVES>::RINGS;
-    static constexpr uint32_t B = Geo<64, uint8_t, K, WAVES>::RINGS;
-    static constexpr uint32_t RINGS = A > B ? A : B;
-};
-
-template <int W, typename Sym, int K, int WAVES>
-__device__ inline void run_item(const DecodeParams &p, unsigned char *smem, const unsigned char *lut, uint32_t wave,
-                                uint32_t lane, uint32_t first, uint32_t count) {
-    using D = PairDecoder<W, Sym, K, WAVES>;
-    D d(p, smem, reinterpret_cast<const typename D::Entry *>(lut), wave * Geo<W, Sym, K, WAVES>::WAVE_LDS, lane);
-    for (uint32_t q = first + wave; q < first + count; q += WAVES) d.run(q);
+template <int W, typename Sym, int K>
+__device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ring0,
+                                uint32_t lane, uint32_t wave, uint32_t waves, uint32_t first, uint32_t count) {
+    PairDecoder<W, Sym, K> d(p, lut, ring0, lane);
+    for (uint32_t q = first + wave; q < first + count; q += waves) d.run(q);
 }
 
 template <int K, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
+    using L = Lds<32, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_item;
-    constexpr uint32_t RINGS = BatchGeo<K, WAVES>::RINGS;
-    unsigned char *lut = smem + RINGS;
+    unsigned char *lut = smem + L::TABLE;
+    const uint32_t base = lds_addr(smem);   // the first word of the pad holds the popped item
     const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ring0 = base + L::PAD + wave * L::WAVE_LDS;
     int32_t cur = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(bp.head, 1u);
+        if (threadIdx.x == 0) lds_st<uint32_t>(base, atomicAdd(bp.head, 1u));
         __syncthreads();
-        const uint32_t it = uni(s_item);
+        const uint32_t it = uni(lds_ld<uint32_t>(base));
         if (it >= bp.n_items) break;
         const WorkItem wi = bp.items[it];
         const StreamDesc d = bp.streams[wi.stream];
         if ((int32_t)wi.stream != cur) {
-            const uint32_t bytes = (d.symbol_bytes == 1 ? 4u : 8u) << d.quant_bits;
+            const uint32_t chunks = ((d.symbol_bytes == 1 ? 4u : 8u) << d.quant_bits) / 16;
             const uint4 *src = reinterpret_cast<const uint4 *>(bp.ws + d.lut_off);
-            uint4 *dst = reinterpret_cast<uint4 *>(lut);
-            for (uint32_t i = threadIdx.x; i < bytes / 16; i += 64 * WAVES) dst[i] = src[i];
+            for (uint32_t i = threadIdx.x; i < chunks; i += 64 * WAVES) reinterpret_cast<uint4 *>(lut)[i] = src[i];
             cur = (int32_t)wi.stream;
         }
         __syncthreads();
@@ -77,11 +69,11 @@ __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
                 else static_cast<uint16_t *>(p.out)[i] = (uint16_t)d.fill_symbol;
             }
         } else if (d.lanes == 32) {
-            if (d.symbol_bytes == 1) run_item<32, uint8_t, K, WAVES>(p, smem, lut, wave, lane, wi.first, wi.count);
-            else run_item<32, uint16_t, K, WAVES>(p, smem, lut, wave, lane, wi.first, wi.count);
+            if (d.symbol_bytes == 1) run_item<32, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            else run_item<32, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
         } else {
-            if (d.symbol_bytes == 1) run_item<64, uint8_t, K, WAVES>(p, smem, lut, wave, lane, wi.first, wi.count);
-            else run_item<64, uint16_t, K, WAVES>(p, smem, lut, wave, lane, wi.first, wi.count);
+            if (d.symbol_bytes == 1) run_item<64, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            else run_item<64, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
         }
         __syncthreads();   // every wave is done with this table before the next item may replace it
     }
@@ -92,10 +84,15 @@ __global__ void reset_head(uint32_t *head) {
 }
 
 template <int K, int WAVES>
+size_t batch_lds(uint32_t lut_bytes) {
+    return Lds<32, K, WAVES>::TABLE + lut_bytes;
+}
+
+template <int K, int WAVES>
 int occupancy(uint32_t lut_bytes) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_batch<K, WAVES>, 64 * WAVES,
-                                                     BatchGeo<K, WAVES>::RINGS + lut_bytes) != hipSuccess)
+                                                     batch_lds<K, WAVES>(lut_bytes)) != hipSuccess)
         return 0;
     return per_cu;
 }
@@ -113,8 +110,8 @@ hipError_t launch(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t str
     if (blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)blocks_per_cu);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(bp.n_items, (uint32_t)(cus * per_cu)));
     hipLaunchKernelGGL(reset_head, dim3(1), dim3(64), 0, stream, bp.head);
-    hipLaunchKernelGGL((decode_batch<K, WAVES>), dim3(blocks), dim3(64 * WAVES),
-                       BatchGeo<K, WAVES>::RINGS + bp.lut_bytes, stream, bp);
+    const size_t lds = batch_lds<K, WAVES>(bp.lut_bytes);
+    hipLaunchKernelGGL((decode_batch<K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, bp);
     return hipGetLastError();
 }
 
@@ -125,7 +122,6 @@ hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t
     if (t.chunk_groups == 4 && t.waves == 8) return launch<4, 8>(bp, t.blocks_per_cu, stream);
     if (t.chunk_groups == 4 && t.waves == 16) return launch<4, 16>(bp, t.blocks_per_cu, stream);
     if (t.chunk_groups == 8 && t.waves == 8) return launch<8, 8>(bp, t.blocks_per_cu, stream);
-    if (t.chunk_groups == 8 && t.waves == 16) return launch<8, 16>(bp, t.blocks_per_cu, stream);
     return hipErrorInvalidValue;
 }
 
@@ -133,7 +129,6 @@ int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes) {
     if (t.chunk_groups == 4 && t.waves == 8) return occupancy<4, 8>(lut_bytes);
     if (t.chunk_groups == 4 && t.waves == 16) return occupancy<4, 16>(lut_bytes);
     if (t.chunk_groups == 8 && t.waves == 8) return occupancy<8, 8>(lut_bytes);
-    if (t.chunk_groups == 8 && t.waves == 16) return occupancy<8, 16>(lut_bytes);
     return 0;
 }
 

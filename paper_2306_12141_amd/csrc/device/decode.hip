@@ -41,20 +41,21 @@ using namespace dev;
 
 template <int W, typename Sym, int K, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void decode_units(DecodeParams p) {
-    using D = PairDecoder<W, Sym, K, WAVES>;
-    using G = Geo<W, Sym, K, WAVES>;
+    using D = PairDecoder<W, Sym, K>;
+    using L = Lds<W, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
-    typename D::Entry *lut = reinterpret_cast<typename D::Entry *>(smem + G::RINGS);
+    unsigned char *lut = smem + L::TABLE;
+    const uint32_t base = lds_addr(smem);
     {
-        const auto *src = static_cast<const typename D::Entry *>(p.lut);
-        const uint32_t slots = 1u << p.quant_bits;
-        for (uint32_t i = threadIdx.x; i < slots; i += 64 * WAVES) lut[i] = src[i];
+        const uint4 *src = static_cast<const uint4 *>(p.lut);
+        const uint32_t chunks = ((uint32_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits) / 16;
+        for (uint32_t i = threadIdx.x; i < chunks; i += 64 * WAVES) reinterpret_cast<uint4 *>(lut)[i] = src[i];
     }
     __syncthreads();
     const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t npairs = (p.units + G::S - 1) / G::S;
-    D d(p, smem, lut, wave * G::WAVE_LDS, lane);
+    const uint32_t npairs = (p.units + D::S - 1) / D::S;
+    D d(p, base + L::TABLE, base + L::PAD + wave * L::WAVE_LDS, lane);
     for (uint32_t pair = blockIdx.x * WAVES + wave; pair < npairs; pair += gridDim.x * WAVES) d.run(pair);
 }
 
@@ -63,30 +64,56 @@ __global__ __launch_bounds__(256) void fill_symbol(Sym *out, uint64_t n, Sym v) 
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) out[i] = v;
 }
 
-template <int W, typename Sym, int K, int WAVES>
-hipError_t launch_units(const DecodeParams &p, hipStream_t stream) {
-    using G = Geo<W, Sym, K, WAVES>;
-    const size_t lds = G::RINGS + ((size_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits);
-    static int per_cu = -1, cus = 0;
-    if (per_cu < 0) {
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
         int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES>, 64 * WAVES,
-                                                         G::RINGS + ((size_t)sizeof(typename Table<Sym>::Entry) << 12)) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 1;
     }
-    const uint32_t pairs = (p.units + G::S - 1) / G::S;
+    return cus;
+}
+
+template <int W, typename Sym, int K, int WAVES>
+size_t lds_bytes(uint32_t quant_bits) {
+    return Lds<W, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
+}
+
+template <int W, typename Sym, int K, int WAVES>
+int units_occupancy(uint32_t quant_bits) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES>, 64 * WAVES,
+                                                     lds_bytes<W, Sym, K, WAVES>(quant_bits)) != hipSuccess)
+        return 0;
+    return per_cu;
+}
+
+template <int W, typename Sym, int K, int WAVES>
+hipError_t launch_units(const DecodeParams &p, uint32_t blocks_per_cu, hipStream_t stream) {
+    int per_cu = units_occupancy<W, Sym, K, WAVES>(p.quant_bits);
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    if (blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)blocks_per_cu);
+    const uint32_t pairs = (p.units + 64 / W - 1) / (64 / W);
     const uint32_t need = (pairs + WAVES - 1) / WAVES;
-    const uint32_t blocks = std::min<uint32_t>(need, (uint32_t)(cus * per_cu));
-    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(std::max(blocks, 1u)), dim3(64 * WAVES), lds, stream, p);
+    const uint32_t blocks = std::max<uint32_t>(1u, std::min<uint32_t>(need, (uint32_t)(device_cus() * per_cu)));
+    const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits);
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, p);
     return hipGetLastError();
+}
+
+template <int W, typename Sym>
+hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream) {
+    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t.blocks_per_cu, stream);
+    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t.blocks_per_cu, stream);
+    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t.blocks_per_cu, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, hipStream_t stream) {
+hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
+                         hipStream_t stream) {
     if (p.n_symbols == 0) return hipSuccess;
     if (p.single_symbol) {
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((p.n_symbols + 255) / 256, 65536);
@@ -98,10 +125,10 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
     }
-    if (lanes == 32 && symbol_bytes == 1) return launch_units<32, uint8_t, 8, 16>(p, stream);
-    if (lanes == 64 && symbol_bytes == 1) return launch_units<64, uint8_t, 8, 16>(p, stream);
-    if (lanes == 32 && symbol_bytes == 2) return launch_units<32, uint16_t, 4, 16>(p, stream);
-    if (lanes == 64 && symbol_bytes == 2) return launch_units<64, uint16_t, 4, 16>(p, stream);
+    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t>(p, t, stream);
+    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t>(p, t, stream);
+    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t>(p, t, stream);
+    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t>(p, t, stream);
     return hipErrorInvalidValue;
 }
 

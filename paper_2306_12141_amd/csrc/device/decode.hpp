@@ -42,7 +42,15 @@ struct DecodeParams {
     uint32_t single_symbol;     // nonzero: the stream is one repeated symbol
 };
 
-// Launchers (decode.hip). Return hipSuccess or the launch error.
-hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, hipStream_t stream);
+// Launch shape of the single-stream kernel: waves per workgroup (8 or 16),
+// groups per super-step K (4 or 8; K = 8 only with 8 waves), workgroups per CU
+// cap (0 = occupancy limit).
+struct DecodeTuning {
+    uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0;
+};
+
+// Launcher (decode.hip). Returns hipSuccess or the launch error.
+hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
+                         hipStream_t stream);
 
 }  // namespace recoil

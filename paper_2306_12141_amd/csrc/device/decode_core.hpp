@@ -1,6 +1,32 @@
-// Device core of the Recoil decoder shared by the single-stream and batched kernels:
-// decode tables, ring geometry and the per-unit-pair decoder (see decode.hip for
-// the design notes).
+// Device core of the Recoil decoder, shared by the single-stream and batched
+// kernels (Lin et al., ICPP 2023, Sec. 4.1; Eq. 2 and Eq. 4).
+//
+// A decode unit is W interleaved rANS lanes; a 64-lane wavefront runs one unit
+// (W = 64) or two (W = 32, one per half-wave). Coder j of a unit lives in wave
+// lane W-1-j of its half, so that "reading lanes with a higher coder index",
+// the words a lane must skip because the decoder consumes words in decreasing
+// coder order (Sec. 2.2), are exactly the reading lanes below it in the wave:
+// its offset is one mbcnt of the read ballot, independent of how many lanes
+// read in total.
+//
+// Bitstream ring (per unit, in LDS). Words are fetched from HBM in chunks of
+// C = K*W words, the most a unit can consume in a super-step of K groups (one
+// word per symbol at most, since b >= n). A chunk is requested into registers
+// at the start of a super-step whenever fewer than 2C words stay resident and is
+// written to the ring at its end. The ring has 3C slots plus a C-word mirror of
+// its top chunk placed below slot 0, so reads never wrap inside a super-step:
+// word w lives at slot w mod 3C, and positions down to -C read the mirror.
+//
+// Per group the scalar unit only tracks U' += 2 * (count of lanes that did not
+// read) (one s_bcnt0 and one s_lshl1_add per unit); the remaining per-group
+// constant moves into the LDS instructions' immediate offsets of the unrolled
+// super-step. The ring read is unconditional and selected with v_cndmask.
+//
+// Synchronisation (Sec. 4.1.1): lane j is switched on with its recorded 16-bit
+// state at the read step of the group its recorded symbol belongs to, just
+// before its first read; groups above the unit's range only advance states.
+// Super-steps holding synchronisation, a ragged last group or the end of a unit
+// run a predicated body; all others the unpredicated one.
 #pragma once
 
 #include <type_traits>
@@ -12,79 +38,100 @@ namespace dev {
 
 constexpr uint32_t kL = 1u << 16;
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kDevErrUnderflow = 1u;
+
+// LDS is addressed with plain 32-bit LDS addresses (address space 3), so that
+// uniform parts of an address stay in SGPRs and constants fold into the
+// instructions' immediate offsets.
+template <typename V>
+__device__ inline V lds_ld(uint32_t a) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) V *>((size_t)a);
+}
+template <typename V>
+__device__ inline void lds_st(uint32_t a, const V &v) {
+    *reinterpret_cast<__attribute__((address_space(3))) V *>((size_t)a) = v;
+}
+__device__ inline uint32_t lds_addr(unsigned char *generic) {
+    return (uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char *)generic;
+}
+
 template <typename Sym>
 struct Table;
 
 template <>
 struct Table<uint8_t> {
-    using Entry = uint32_t;
-    __device__ static inline uint32_t step(const Entry *lut, uint32_t &x, uint32_t n, uint32_t mask) {
-        const Entry e = lut[x & mask];
+    using Entry = uint32_t;   // symbol | f << 8 | (slot - F) << 20
+    __device__ static inline uint32_t step(uint32_t lut, uint32_t &x, uint32_t n, uint32_t mask) {
+        const Entry e = lds_ld<Entry>(lut + ((x & mask) << 2));
         const uint32_t f = (e >> 8) & 0xFFFu;
-        const uint32_t off = e >> 20;
-        x = __umul24(f, x >> n) + off;
-        return e;           // low byte is the symbol
+        x = __umul24(f, x >> n) + (e >> 20);
+        return e;             // the low byte is the symbol
     }
 };
 
 template <>
 struct Table<uint16_t> {
-    using Entry = uint2;
-    __device__ static inline uint32_t step(const Entry *lut, uint32_t &x, uint32_t n, uint32_t mask) {
-        const Entry e = lut[x & mask];
-        const uint32_t f = e.x & 0xFFFFu;
-        const uint32_t off = e.x >> 16;
-        x = __umul24(f, x >> n) + off;
+    using Entry = u32x2;      // .x = f | (slot - F) << 16, .y = symbol
+    __device__ static inline uint32_t step(uint32_t lut, uint32_t &x, uint32_t n, uint32_t mask) {
+        const Entry e = lds_ld<Entry>(lut + ((x & mask) << 3));
+        x = __umul24(e.x & 0xFFFFu, x >> n) + (e.x >> 16);
         return e.y;
     }
 };
 
-template <int W, typename Sym, int K, int WAVES>
+template <int W, int K>
 struct Geo {
-    static constexpr uint32_t S = 64 / W;                 // units per wave
-    static constexpr uint32_t C = K * W;                  // chunk words
-    static constexpr uint32_t R = 3 * C;                  // ring words
-    static constexpr uint32_t RING = R + 64;              // ring words incl. mirror
-    static constexpr uint32_t WAVE_LDS = S * RING * 2;    // bytes of rings per wave
-    static constexpr uint32_t RINGS = WAVES * WAVE_LDS;   // bytes of rings per workgroup
-    static constexpr uint32_t LANE_BYTES = 2 * K;         // chunk bytes per lane
-    using Chunk = typename std::conditional<LANE_BYTES == 16, uint4, uint2>::type;
+    static constexpr uint32_t S = 64 / W;             // units per wave
+    static constexpr uint32_t C = K * W;              // chunk words
+    static constexpr uint32_t R = 3 * C;              // ring slots
+    static constexpr uint32_t UNIT = 2 * (C + R);     // LDS bytes per unit: mirror + ring
+    static constexpr uint32_t WAVE_LDS = S * UNIT;
+    static constexpr uint32_t LANE_BYTES = 2 * K;     // chunk bytes per lane of a unit
+    using Chunk = typename std::conditional<LANE_BYTES == 16, u32x4, u32x2>::type;
     static_assert(sizeof(Chunk) == LANE_BYTES, "chunk slice must be 8 or 16 bytes");
-    static_assert(C >= 64, "mirror needs chunks of at least 64 words");
-    static_assert(RINGS < 65536, "rings must leave the table at a 16-bit LDS offset");
+};
+
+// LDS layout of a workgroup: [pad][rings of every wave][decode table].
+template <int WMIN, int K, int WAVES>
+struct Lds {
+    static constexpr uint32_t PAD = 2 * K * 64;       // keeps (address - immediate offset) >= 0
+    static constexpr uint32_t WAVE_LDS = Geo<32, K>::WAVE_LDS > Geo<64, K>::WAVE_LDS ? Geo<32, K>::WAVE_LDS
+                                                                                     : Geo<64, K>::WAVE_LDS;
+    static constexpr uint32_t TABLE = PAD + WAVES * WAVE_LDS;
+    static_assert(TABLE < 65536, "the table must sit at a 16-bit LDS offset");
 };
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <int W, typename Sym, int K, int WAVES>
+template <int W, typename Sym, int K>
 struct PairDecoder {
-    using G = Geo<W, Sym, K, WAVES>;
+    using G = Geo<W, K>;
     using T = Table<Sym>;
-    using Entry = typename T::Entry;
     using Chunk = typename G::Chunk;
-    static constexpr uint32_t S = G::S, C = G::C, R = G::R, RING = G::RING;
+    static constexpr uint32_t S = G::S, C = G::C, R = G::R;
 
     const DecodeParams &p;
-    unsigned char *smem;
-    const Entry *lut;
-    uint32_t ring0;        // byte offset of this wave's rings in LDS
-    uint32_t lane, j, upper;
+    uint32_t lut;          // LDS address of the decode table
+    uint32_t ring0;        // LDS address of this wave's first unit (mirror start)
+    uint32_t lane, col, upper, coder;
     uint32_t n, mask;
 
     // Per unit of the pair (wave-uniform).
     uint32_t valid[S], last[S], top[S], ghi[S], steps[S], sync[S];
-    int32_t nxt[S];        // words left below the cursor (first unread word is nxt - 1)
-    uint32_t slotn[S];     // ring slot of word nxt (mod R)
+    int32_t cur[S];        // words remaining: the next word to read is cur - 1
+    int32_t stop[S];       // ring slot of word cur - 1 (in [0, R))
     int32_t fq[S];         // lowest chunk held in the ring
     // Per lane.
     uint32_t x, rec, act;
     bool active;
 
-    __device__ PairDecoder(const DecodeParams &p_, unsigned char *smem_, const Entry *lut_, uint32_t ring0_,
-                           uint32_t lane_)
-        : p(p_), smem(smem_), lut(lut_), ring0(ring0_), lane(lane_) {
-        j = lane & (W - 1);
+    __device__ PairDecoder(const DecodeParams &p_, uint32_t lut_, uint32_t ring0_, uint32_t lane_)
+        : p(p_), lut(lut_), ring0(ring0_), lane(lane_) {
+        col = lane & (W - 1);
         upper = (W == 32) ? (lane >> 5) : 0u;
+        coder = W - 1 - col;
         n = p.quant_bits;
         mask = (1u << n) - 1u;
     }
@@ -95,17 +142,34 @@ struct PairDecoder {
         else return h ? a[1] : a[0];
     }
 
-    __device__ inline uint32_t ring_byte(uint32_t h, uint32_t slot) const { return ring0 + 2u * (h * RING + slot); }
-
-    __device__ inline const Chunk *chunk_src(int32_t q) const {
-        return reinterpret_cast<const Chunk *>(p.words + (uint64_t)(uint32_t)q * C) + j;
+    // LDS byte address of ring position s (s in [-C, R)) of unit h. The ring is
+    // stored in descending order (slot R-1 lowest, the mirror of slots 2C..3C-1
+    // above slot 0), so consecutive reads of a group go upwards in LDS.
+    __device__ inline uint32_t ring_addr(uint32_t h, int32_t s) const {
+        return ring0 + h * G::UNIT + 2u * (uint32_t)((int32_t)R - 1 - s);
     }
 
-    // Write one chunk slice (this lane's part of chunk q) into the ring, and its mirror copy.
+    __device__ inline const Chunk *chunk_src(int32_t q) const {
+        return reinterpret_cast<const Chunk *>(p.words + (uint64_t)(uint32_t)q * C) + col;
+    }
+
+    // This lane's slice of chunk q (K words, ascending) into the ring with its
+    // words reversed, and into the mirror for chunks in the top third.
     __device__ inline void put_chunk(int32_t q, const Chunk &v) {
-        const uint32_t slot = (uint32_t)(q % 3) * C + K * j;
-        *reinterpret_cast<Chunk *>(smem + ring_byte(upper, slot)) = v;
-        if (slot < 64) *reinterpret_cast<Chunk *>(smem + ring_byte(upper, R + slot)) = v;
+        Chunk r16;
+        if constexpr (K == 4) {
+            r16.x = __builtin_amdgcn_alignbit(v.y, v.y, 16);
+            r16.y = __builtin_amdgcn_alignbit(v.x, v.x, 16);
+        } else {
+            r16.x = __builtin_amdgcn_alignbit(v.w, v.w, 16);
+            r16.y = __builtin_amdgcn_alignbit(v.z, v.z, 16);
+            r16.z = __builtin_amdgcn_alignbit(v.y, v.y, 16);
+            r16.w = __builtin_amdgcn_alignbit(v.x, v.x, 16);
+        }
+        const int32_t r = q % 3;
+        const int32_t slot = r * (int32_t)C + (int32_t)(K * col) + (int32_t)K - 1;   // lowest address of the slice
+        lds_st<Chunk>(ring_addr(upper, slot), r16);
+        if (r == 2) lds_st<Chunk>(ring_addr(upper, slot - (int32_t)R), r16);
     }
 
     __device__ bool begin(uint32_t pair) {
@@ -118,7 +182,7 @@ struct PairDecoder {
             last[h] = valid[h] && u + 1 == p.units;
             UnitMeta m = {0, 0, 0, 1};
             if (valid[h]) m = p.meta[u];
-            nxt[h] = (int32_t)uni(m.next);
+            cur[h] = (int32_t)uni(m.next);
             top[h] = uni(m.top);
             ghi[h] = uni(m.ghi);
             const uint32_t glo = uni(m.glo);
@@ -129,20 +193,20 @@ struct PairDecoder {
         }
         const uint32_t my_valid = pick(valid, upper);
         const uint32_t my_last = pick(last, upper);
-        rec = my_valid ? p.lanes[(uint64_t)(u0 + upper) * W + j] : 0u;
+        rec = my_valid ? p.lanes[(uint64_t)(u0 + upper) * W + coder] : 0u;
         x = my_last ? rec : 0u;
         active = my_last != 0;
         act = my_last ? 0u : (rec >> 16);
-        // Initial ring fill: the chunk holding word nxt-1 and the two below it.
+        // Initial fill: the chunk holding word cur-1 and the two below it.
         int32_t q0[S];
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
-            q0[h] = nxt[h] > 0 ? (nxt[h] - 1) / (int32_t)C : -1;
+            q0[h] = cur[h] > 0 ? (cur[h] - 1) / (int32_t)C : -1;
             fq[h] = q0[h] >= 2 ? q0[h] - 2 : 0;
-            slotn[h] = (uint32_t)nxt[h] % R;
+            stop[h] = cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0;
         }
         const int32_t my_q0 = pick(q0, upper);
-        Chunk c0{}, c1{}, c2{};
+        Chunk c0 = {}, c1 = {}, c2 = {};
         if (my_q0 >= 0) c0 = *chunk_src(my_q0);
         if (my_q0 >= 1) c1 = *chunk_src(my_q0 - 1);
         if (my_q0 >= 2) c2 = *chunk_src(my_q0 - 2);
@@ -152,89 +216,119 @@ struct PairDecoder {
         return any;
     }
 
-    // Read step for one group: ballot, consumed-word bookkeeping, per-lane ring address.
-    __device__ inline void read_step(bool need) {
+    // One group's read step. ua (and e, for unit B when W = 32) is the LDS
+    // address of the unit's next word to read; need is this lane's "x < L" (and live).
+    template <uint32_t G_IDX>
+    __device__ inline void read_step(bool need, uint32_t &ua, uint32_t &e) {
         const uint64_t bal = __ballot(need);
         const uint32_t bl = (uint32_t)bal, bh = (uint32_t)(bal >> 32);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl, 0u));
+        const uint32_t m = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl, 0u));
+        // The lane's word is m words above the unit's top word (descending ring).
+        // ua/e stay opaque SGPR byte addresses so each address is one v_lshl_add.
+        asm volatile("" : "+s"(ua));
+        if constexpr (W == 32) asm volatile("" : "+s"(e));
         uint32_t addr;
         if constexpr (W == 64) {
-            const uint32_t cnt = __popcll(bal);
-            uint32_t bs = slotn[0] - cnt;
-            if ((int32_t)bs < 0) bs += R;
-            slotn[0] = bs;
-            nxt[0] -= (int32_t)cnt;
-            addr = (below << 1) + ring_byte(0, bs);
+            addr = (m << 1) + ua;
+            ua += 2u * (uint32_t)__builtin_popcountll(bal);
         } else {
-            const uint32_t cA = __popc(bl), cB = __popc(bh);
-            uint32_t bsA = slotn[0] - cA, bsB = slotn[1] - cB;
-            if ((int32_t)bsA < 0) bsA += R;
-            if ((int32_t)bsB < 0) bsB += R;
-            slotn[0] = bsA;
-            slotn[1] = bsB;
-            nxt[0] -= (int32_t)cA;
-            nxt[1] -= (int32_t)cB;
-            // Upper lanes count the lower half's readers too: fold that into their offset.
-            const uint32_t dW = (RING + bsB - cA) - bsA;
-            addr = ((__umul24(upper, dW) + below) << 1) + ring_byte(0, bsA);
+            // Upper lanes' m also counts unit A's readers; unit A's advance cancels them.
+            const uint32_t ua_next = ua + 2u * (uint32_t)__builtin_popcount(bl);
+            const uint32_t d = e - ua_next;                         // e is unit B's top address
+            uint32_t t = (m << 1) + ua;
+            asm volatile("" : "+v"(t));                             // keep v_lshl_add + v_mad_u32_u24
+            addr = __umul24(upper, d) + t;
+            ua = ua_next;
+            e += 2u * (uint32_t)__builtin_popcount(bh);
         }
-        if (need) x = (x << 16) | *reinterpret_cast<const uint16_t *>(smem + addr);
+        uint32_t w = lds_ld<uint16_t>(addr);
+        // Keep the read unconditional: lanes that do not need it read an in-ring word and drop it.
+        asm volatile("" : "+v"(w));
+        x = need ? ((x << 16) | w) : x;
     }
 
-    __device__ inline void group_fast(unsigned char *outh, uint32_t lane_off) {
-        read_step(x < kL);
+    // Super-step start: LDS address of each unit's top word.
+    __device__ inline void step_bases(uint32_t &ua, uint32_t &e) const {
+        ua = uni(ring_addr(0, stop[0]));
+        if constexpr (S == 2) e = uni(ring_addr(1, stop[1]));
+        else e = 0;
+    }
+
+    // Super-step end: words consumed per unit from the top-address advance.
+    __device__ inline void step_advance(uint32_t ua0, uint32_t ua, uint32_t e0, uint32_t e) {
+        const int32_t ca = (int32_t)((ua - ua0) >> 1);
+        cur[0] -= ca;
+        stop[0] -= ca;
+        if (stop[0] < 0) stop[0] += (int32_t)R;
+        if constexpr (S == 2) {
+            const int32_t cb = (int32_t)((e - e0) >> 1);
+            cur[1] -= cb;
+            stop[1] -= cb;
+            if (stop[1] < 0) stop[1] += (int32_t)R;
+        }
+    }
+
+    template <uint32_t G_IDX>
+    __device__ inline void group_fast(uint32_t &ua, uint32_t &e, unsigned char *outh, uint32_t lane_off) {
+        read_step<G_IDX>(x < kL, ua, e);
         const uint32_t s = T::step(lut, x, n, mask);
-        *reinterpret_cast<Sym *>(outh + lane_off) = (Sym)s;
+        *reinterpret_cast<Sym *>(outh + lane_off - G_IDX * W * sizeof(Sym)) = (Sym)s;
     }
 
-    __device__ inline void group_pred(uint32_t k) {
-        const uint32_t my_steps = pick(steps, upper);
-        const bool live = k < my_steps;
+    template <uint32_t G_IDX>
+    __device__ inline void group_pred(uint32_t k, uint32_t &ua, uint32_t &e) {
+        const bool live = k < pick(steps, upper);
         if (live && !active && k == act) {
             active = true;
             x = rec & 0xFFFFu;
         }
-        read_step(live && active && x < kL);
+        read_step<G_IDX>(live && active && x < kL, ua, e);
         const uint32_t h = pick(top, upper) - k;
-        const uint64_t i = (uint64_t)h * W + j;
+        const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
             const uint32_t s = T::step(lut, x, n, mask);
             if (h <= pick(ghi, upper)) static_cast<Sym *>(p.out)[i] = (Sym)s;
         }
     }
 
+    template <bool PRED, uint32_t... G_IDX>
+    __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &ua, uint32_t &e,
+                                  unsigned char *outh, uint32_t lane_off) {
+        if constexpr (PRED) (group_pred<G_IDX>(k + G_IDX, ua, e), ...);
+        else (group_fast<G_IDX>(ua, e, outh, lane_off), ...);
+    }
+
     template <bool PRED>
     __device__ inline bool super_step(uint32_t k) {
-        // Prefetch the next chunk of any unit that has fewer than 2C words resident.
+        // Prefetch the next chunk of any unit with fewer than 2C words resident.
         bool ld[S];
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
-            ld[h] = steps[h] > k && fq[h] > 0 && nxt[h] - fq[h] * (int32_t)C < 2 * (int32_t)C;
+            ld[h] = steps[h] > k && fq[h] > 0 && cur[h] - fq[h] * (int32_t)C < 2 * (int32_t)C;
         const bool my_ld = pick(ld, upper);
         const int32_t my_q = pick(fq, upper) - 1;
-        Chunk pre{};
+        Chunk pre = {};
         if (my_ld) pre = *chunk_src(my_q);
-        if constexpr (PRED) {
-#pragma unroll
-            for (uint32_t g = 0; g < K; ++g) group_pred(k + g);
-        } else {
-            // Unit A's group pointer is uniform; unit B's offset from it is per lane and fixed.
-            unsigned char *outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top[0] - k) * W * sizeof(Sym);
-            uint32_t lane_off = j;
+        uint32_t ua, e;
+        step_bases(ua, e);
+        const uint32_t ua0 = ua, e0 = e;
+        unsigned char *outh = nullptr;
+        uint32_t lane_off = 0;
+        if constexpr (!PRED) {
+            // Unit A's group pointer is uniform; each lane's offset from it is fixed.
+            outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top[0] - k) * W * sizeof(Sym);
+            lane_off = coder;
             if constexpr (S == 2) lane_off += upper * W * (top[1] - top[0]);
             lane_off *= sizeof(Sym);
-#pragma unroll
-            for (uint32_t g = 0; g < K; ++g) {
-                group_fast(outh, lane_off);
-                outh -= W * sizeof(Sym);
-            }
         }
+        groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, ua, e, outh, lane_off);
+        step_advance(ua0, ua, e0, e);
         if (my_ld) put_chunk(my_q, pre);
         bool ok = true;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             if (ld[h]) fq[h] -= 1;
-            if (valid[h] && nxt[h] < 0) ok = false;    // ran below the first word: corrupt split data
+            if (valid[h] && cur[h] < 0) ok = false;   // read below the first word: corrupt split data
         }
         return ok;
     }
@@ -252,15 +346,12 @@ struct PairDecoder {
             const bool pred = k < presync || k + K > kmin;
             const bool ok = pred ? super_step<true>(k) : super_step<false>(k);
             if (!ok) {
-                if (lane == 0) atomicOr(p.err, RECOIL_DEVERR_UNDERFLOW_BIT);
+                if (lane == 0) atomicOr(p.err, kDevErrUnderflow);
                 return;
             }
         }
     }
-
-    static constexpr uint32_t RECOIL_DEVERR_UNDERFLOW_BIT = 1u;
 };
-
 
 }  // namespace dev
 }  // namespace recoil

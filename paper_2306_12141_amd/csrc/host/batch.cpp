@@ -245,7 +245,7 @@ recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const vo
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
         p.single_symbol = d.single_symbol;
-        hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, stream);
+        hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
         if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch_per_stream: ") + hipGetErrorString(e));
     }
     return RECOIL_OK;

@@ -133,6 +133,17 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t byt
 
 void recoil_plan_free(recoil_plan *plan) { delete plan; }
 
+recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *t) {
+    using namespace recoil;
+    if (!plan || !t) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: bad arguments");
+    const bool ok = (t->waves == 16 && t->chunk_groups == 4) || (t->waves == 8 && (t->chunk_groups == 4 || t->chunk_groups == 8));
+    if (!ok) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: unsupported shape");
+    plan->d.tuning.waves = t->waves;
+    plan->d.tuning.chunk_groups = t->chunk_groups;
+    plan->d.tuning.blocks_per_cu = t->blocks_per_cu;
+    return RECOIL_OK;
+}
+
 recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_out, uint32_t *d_error,
                             hipStream_t stream) {
     using namespace recoil;
@@ -155,7 +166,7 @@ recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_o
     p.quant_bits = b.quant_bits;
     p.fill_symbol = pl.fill_symbol;
     p.single_symbol = pl.single_symbol ? 1u : 0u;
-    hipError_t e = launch_decode(p, b.lanes, b.symbol_bytes, stream);
+    hipError_t e = launch_decode(p, b.lanes, b.symbol_bytes, pl.tuning, stream);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode: ") + hipGetErrorString(e));
     return RECOIL_OK;
 }

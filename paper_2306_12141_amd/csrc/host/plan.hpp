@@ -15,6 +15,7 @@ struct PlanData {
     std::vector<UnitMeta> meta;          // M
     std::vector<uint32_t> lanes;         // M x W
     std::vector<uint8_t> lut;            // 2^n entries, 4 or 8 bytes each
+    DecodeTuning tuning;                 // launch shape for recoil_decode
     bool single_symbol = false;
     uint32_t fill_symbol = 0;
     // Workspace layout of a single-stream plan (byte offsets from the workspace base).
