@@ -126,6 +126,9 @@ def run_c1(args, torch, np, rc, synth):
     log(f"encoded: {info.n_words} words, {info.splits} splits, metadata {info.metadata_bytes} B "
         f"in {time.perf_counter() - t0:.1f}s")
     plan = rc.Plan(blob)
+    if args.shape:
+        w, k, b = (int(v) for v in args.shape.split(","))
+        plan.set_tuning(waves=w, chunk_groups=k, blocks_per_cu=b)
     ws = plan.allocate_workspace()
     plan.upload(ws)
     out = plan.allocate_output()
@@ -178,6 +181,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--lanes", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU",
+                    help="launch shape of the decode kernel (default 16,4,0)")
     ap.add_argument("--workload", default="c1", choices=("c1",))
     ap.add_argument("--no-extras", action="store_true", help="skip the W=64 and combined-split runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -101,7 +101,7 @@ typedef struct {
  *   waves          waves per workgroup (8 or 16); the waves of a workgroup share one
  *                  decode table in LDS
  *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
- *                  ring holds 4 K W words (3 K W ring + K W mirror). K = 8 needs waves = 8
+ *                  ring holds 4 K W words (3 K W ring + K W mirror)
  *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)
  *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit) */
 typedef struct {

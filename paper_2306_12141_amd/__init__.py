@@ -137,6 +137,10 @@ class Plan:
     def metadata_device_bytes(self) -> int:
         return _lib.recoil_plan_metadata_device_bytes(self._h)
 
+    def set_tuning(self, waves: int = 16, chunk_groups: int = 4, blocks_per_cu: int = 0) -> None:
+        t = _lib.Tuning(waves, chunk_groups, 1, blocks_per_cu)
+        check(_lib.recoil_plan_set_tuning(self._h, C.byref(t)), "recoil_plan_set_tuning")
+
     def allocate_workspace(self, device="cuda"):
         import torch
         return torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=device)

@@ -71,3 +71,25 @@ class RecoilError(RuntimeError):
 def check(status: int, what: str) -> None:
     if status != 0:
         raise RecoilError(status, what)
+
+
+class Tuning(C.Structure):
+    _fields_ = [("waves", u32), ("chunk_groups", u32), ("pairs_per_wave", u32), ("blocks_per_cu", u32)]
+
+
+recoil_plan_set_tuning = _sig("recoil_plan_set_tuning", [P, C.POINTER(Tuning)])
+recoil_default_tuning = _sig("recoil_default_tuning", [], Tuning)
+recoil_batch_create = _sig("recoil_batch_create", [P, u32, C.POINTER(Tuning), C.POINTER(P), C.POINTER(sz),
+                                                   C.POINTER(sz)])
+recoil_batch_free = _sig("recoil_batch_free", [P], None)
+recoil_batch_output_offset = _sig("recoil_batch_output_offset", [P, u32, C.POINTER(u64), C.POINTER(u64)])
+recoil_batch_items = _sig("recoil_batch_items", [P], u32)
+recoil_batch_upload = _sig("recoil_batch_upload", [P, P, sz, P])
+recoil_batch_set_tuning = _sig("recoil_batch_set_tuning", [P, C.POINTER(Tuning), P, P])
+recoil_batch_get_tuning = _sig("recoil_batch_get_tuning", [P, C.POINTER(Tuning)])
+recoil_decode_batch = _sig("recoil_decode_batch", [P, P, P, P, P])
+recoil_decode_batch_per_stream = _sig("recoil_decode_batch_per_stream", [P, P, P, P, P])
+recoil_batch_graph_create = _sig("recoil_batch_graph_create", [P, P, P, P, C.POINTER(P)])
+recoil_graph_launch = _sig("recoil_graph_launch", [P, P])
+recoil_graph_free = _sig("recoil_graph_free", [P], None)
+recoil_autotune = _sig("recoil_autotune", [P, P, P, P, P, u32, C.POINTER(Tuning), C.POINTER(C.c_float)])

@@ -29,7 +29,7 @@ __device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ri
 
 template <int K, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
-    using L = Lds<32, K, WAVES>;
+    using L = Lds<16, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
     const uint32_t base = lds_addr(smem);   // the first word of the pad holds the popped item
@@ -85,7 +85,7 @@ __global__ void reset_head(uint32_t *head) {
 
 template <int K, int WAVES>
 size_t batch_lds(uint32_t lut_bytes) {
-    return Lds<32, K, WAVES>::TABLE + lut_bytes;
+    return Lds<16, K, WAVES>::TABLE + lut_bytes;
 }
 
 template <int K, int WAVES>
@@ -122,6 +122,7 @@ hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t
     if (t.chunk_groups == 4 && t.waves == 8) return launch<4, 8>(bp, t.blocks_per_cu, stream);
     if (t.chunk_groups == 4 && t.waves == 16) return launch<4, 16>(bp, t.blocks_per_cu, stream);
     if (t.chunk_groups == 8 && t.waves == 8) return launch<8, 8>(bp, t.blocks_per_cu, stream);
+    if (t.chunk_groups == 8 && t.waves == 16) return launch<8, 16>(bp, t.blocks_per_cu, stream);
     return hipErrorInvalidValue;
 }
 
@@ -129,6 +130,7 @@ int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes) {
     if (t.chunk_groups == 4 && t.waves == 8) return occupancy<4, 8>(lut_bytes);
     if (t.chunk_groups == 4 && t.waves == 16) return occupancy<4, 16>(lut_bytes);
     if (t.chunk_groups == 8 && t.waves == 8) return occupancy<8, 8>(lut_bytes);
+    if (t.chunk_groups == 8 && t.waves == 16) return occupancy<8, 16>(lut_bytes);
     return 0;
 }
 

@@ -42,7 +42,7 @@ using namespace dev;
 template <int W, typename Sym, int K, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void decode_units(DecodeParams p) {
     using D = PairDecoder<W, Sym, K>;
-    using L = Lds<W, K, WAVES>;
+    using L = Lds<0, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
     const uint32_t base = lds_addr(smem);
@@ -77,7 +77,7 @@ int device_cus() {
 
 template <int W, typename Sym, int K, int WAVES>
 size_t lds_bytes(uint32_t quant_bits) {
-    return Lds<W, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
+    return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
 }
 
 template <int W, typename Sym, int K, int WAVES>
@@ -107,6 +107,7 @@ hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_
     if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t.blocks_per_cu, stream);
     if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t.blocks_per_cu, stream);
     if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t.blocks_per_cu, stream);
+    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16>(p, t.blocks_per_cu, stream);
     return hipErrorInvalidValue;
 }
 

@@ -43,7 +43,7 @@ struct DecodeParams {
 };
 
 // Launch shape of the single-stream kernel: waves per workgroup (8 or 16),
-// groups per super-step K (4 or 8; K = 8 only with 8 waves), workgroups per CU
+// groups per super-step K (4 or 8), workgroups per CU
 // cap (0 = occupancy limit).
 struct DecodeTuning {
     uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0;

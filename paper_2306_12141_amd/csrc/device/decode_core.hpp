@@ -93,14 +93,14 @@ struct Geo {
     static_assert(sizeof(Chunk) == LANE_BYTES, "chunk slice must be 8 or 16 bytes");
 };
 
-// LDS layout of a workgroup: [pad][rings of every wave][decode table].
-template <int WMIN, int K, int WAVES>
+// LDS layout of a workgroup: [pad][rings of every wave][decode table]. The
+// pad is a 16-byte slot the batched kernel uses to broadcast its work item.
+template <int PADB, int K, int WAVES>
 struct Lds {
-    static constexpr uint32_t PAD = 2 * K * 64;       // keeps (address - immediate offset) >= 0
+    static constexpr uint32_t PAD = PADB;
     static constexpr uint32_t WAVE_LDS = Geo<32, K>::WAVE_LDS > Geo<64, K>::WAVE_LDS ? Geo<32, K>::WAVE_LDS
                                                                                      : Geo<64, K>::WAVE_LDS;
     static constexpr uint32_t TABLE = PAD + WAVES * WAVE_LDS;
-    static_assert(TABLE < 65536, "the table must sit at a 16-bit LDS offset");
 };
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -116,6 +116,7 @@ struct PairDecoder {
     uint32_t lut;          // LDS address of the decode table
     uint32_t ring0;        // LDS address of this wave's first unit (mirror start)
     uint32_t lane, col, upper, coder;
+    uint32_t lane_ring;    // this lane's chunk-slice address in the top third of its unit's ring
     uint32_t n, mask;
 
     // Per unit of the pair (wave-uniform).
@@ -134,6 +135,7 @@ struct PairDecoder {
         coder = W - 1 - col;
         n = p.quant_bits;
         mask = (1u << n) - 1u;
+        lane_ring = lane_ring_addr();
     }
 
     template <typename V>
@@ -149,13 +151,17 @@ struct PairDecoder {
         return ring0 + h * G::UNIT + 2u * (uint32_t)((int32_t)R - 1 - s);
     }
 
-    __device__ inline const Chunk *chunk_src(int32_t q) const {
-        return reinterpret_cast<const Chunk *>(p.words + (uint64_t)(uint32_t)q * C) + col;
+    // This lane's slice of chunk q (uniform q): a scalar base plus a fixed lane offset.
+    __device__ inline Chunk fetch(int32_t q) const {
+        const unsigned char *base = reinterpret_cast<const unsigned char *>(p.words) + (uint64_t)(uint32_t)q * (2 * C);
+        return *reinterpret_cast<const Chunk *>(base + col * (uint32_t)sizeof(Chunk));
     }
 
-    // This lane's slice of chunk q (K words, ascending) into the ring with its
-    // words reversed, and into the mirror for chunks in the top third.
-    __device__ inline void put_chunk(int32_t q, const Chunk &v) {
+    // This lane's slice (K words, ascending) into the ring of its unit with the
+    // words reversed, for chunk q (uniform). lane_ring is the lane's slice
+    // address for chunks in the top third; the other thirds and the mirror are
+    // fixed offsets from it, chosen by the scalar q mod 3.
+    __device__ inline void put_chunk(int32_t q, const Chunk &v, uint32_t lane_ring) {
         Chunk r16;
         if constexpr (K == 4) {
             r16.x = __builtin_amdgcn_alignbit(v.y, v.y, 16);
@@ -167,9 +173,25 @@ struct PairDecoder {
             r16.w = __builtin_amdgcn_alignbit(v.x, v.x, 16);
         }
         const int32_t r = q % 3;
-        const int32_t slot = r * (int32_t)C + (int32_t)(K * col) + (int32_t)K - 1;   // lowest address of the slice
-        lds_st<Chunk>(ring_addr(upper, slot), r16);
-        if (r == 2) lds_st<Chunk>(ring_addr(upper, slot - (int32_t)R), r16);
+        if (r == 2) {
+            lds_st<Chunk>(lane_ring, r16);
+            lds_st<Chunk>(lane_ring + 6 * C, r16);     // mirror, below slot 0
+        } else if (r == 1) {
+            lds_st<Chunk>(lane_ring + 2 * C, r16);
+        } else {
+            lds_st<Chunk>(lane_ring + 4 * C, r16);
+        }
+    }
+
+    // Lane slice address for chunks in the top third of the ring.
+    __device__ inline uint32_t lane_ring_addr() const { return ring_addr(upper, 2 * (int32_t)C + (int32_t)(K * col + K - 1)); }
+
+    // Chunk q of unit h into the ring: only the lanes of unit h take part.
+    __device__ inline void load_put(uint32_t h, int32_t q, uint32_t lane_ring) {
+        if (S == 1 || upper == h) {
+            const Chunk v = fetch(q);
+            put_chunk(q, v, lane_ring);
+        }
     }
 
     __device__ bool begin(uint32_t pair) {
@@ -205,14 +227,9 @@ struct PairDecoder {
             fq[h] = q0[h] >= 2 ? q0[h] - 2 : 0;
             stop[h] = cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0;
         }
-        const int32_t my_q0 = pick(q0, upper);
-        Chunk c0 = {}, c1 = {}, c2 = {};
-        if (my_q0 >= 0) c0 = *chunk_src(my_q0);
-        if (my_q0 >= 1) c1 = *chunk_src(my_q0 - 1);
-        if (my_q0 >= 2) c2 = *chunk_src(my_q0 - 2);
-        if (my_q0 >= 0) put_chunk(my_q0, c0);
-        if (my_q0 >= 1) put_chunk(my_q0 - 1, c1);
-        if (my_q0 >= 2) put_chunk(my_q0 - 2, c2);
+#pragma unroll
+        for (uint32_t h = 0; h < S; ++h)
+            for (int32_t q = q0[h]; q >= 0 && q > q0[h] - 3; --q) load_put(h, q, lane_ring);
         return any;
     }
 
@@ -305,10 +322,27 @@ struct PairDecoder {
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
             ld[h] = steps[h] > k && fq[h] > 0 && cur[h] - fq[h] * (int32_t)C < 2 * (int32_t)C;
-        const bool my_ld = pick(ld, upper);
-        const int32_t my_q = pick(fq, upper) - 1;
-        Chunk pre = {};
-        if (my_ld) pre = *chunk_src(my_q);
+        // Each unit's lanes fetch their own slice with a scalar base; one register
+        // set suffices because the two units of a pair use disjoint lanes.
+        // One load instruction for the whole wave (each unit's lanes address their
+        // own chunk), issued whenever any unit needs one. Its registers are not
+        // touched again before the end of the super-step, so the load overlaps
+        // the K groups; a conditional or split load would make the compiler copy
+        // the destination, and a copy waits (vmcnt) for the load and the stores.
+        bool any_ld = false;
+#pragma unroll
+        for (uint32_t h = 0; h < S; ++h) any_ld = any_ld || ld[h];
+        Chunk pre;
+        if (any_ld) {
+            const uint32_t qa = (uint32_t)max(fq[0] - 1, 0);
+            uint64_t off = (uint64_t)qa * (2 * C);
+            if constexpr (S == 2) {
+                const uint32_t qb = (uint32_t)max(fq[1] - 1, 0);
+                off = upper ? (uint64_t)qb * (2 * C) : off;
+            }
+            pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) + off +
+                                                   col * (uint32_t)sizeof(Chunk));
+        }
         uint32_t ua, e;
         step_bases(ua, e);
         const uint32_t ua0 = ua, e0 = e;
@@ -323,11 +357,23 @@ struct PairDecoder {
         }
         groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, ua, e, outh, lane_off);
         step_advance(ua0, ua, e0, e);
-        if (my_ld) put_chunk(my_q, pre);
+        // The fetched chunks are consumed only here, K groups after their
+        // request: the empty asm keeps the scheduler from hoisting their use
+        // (and its wait on the load) into the groups above.
+        if (any_ld) {
+            asm volatile("" : "+v"(pre));
+#pragma unroll
+            for (uint32_t h = 0; h < S; ++h)
+                if (ld[h] && (S == 1 || upper == h)) put_chunk(fq[h] - 1, pre, lane_ring);
+        }
         bool ok = true;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             if (ld[h]) fq[h] -= 1;
+            // The unit bookkeeping is wave-uniform; say so, so it stays in SGPRs.
+            fq[h] = (int32_t)uni((uint32_t)fq[h]);
+            cur[h] = (int32_t)uni((uint32_t)cur[h]);
+            stop[h] = (int32_t)uni((uint32_t)stop[h]);
             if (valid[h] && cur[h] < 0) ok = false;   // read below the first word: corrupt split data
         }
         return ok;

@@ -28,6 +28,11 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N and B must be below 2^32");
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
     pl.blob = bp;
+    // Default launch shape: 16 waves with 8-group super-steps when the table is
+    // small enough for two workgroups per CU (uint8 symbols), 4-group otherwise.
+    pl.tuning.waves = 16;
+    pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
+    pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
     pl.meta.resize(M);
     pl.lanes.resize((size_t)M * W);
@@ -136,7 +141,7 @@ void recoil_plan_free(recoil_plan *plan) { delete plan; }
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *t) {
     using namespace recoil;
     if (!plan || !t) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: bad arguments");
-    const bool ok = (t->waves == 16 && t->chunk_groups == 4) || (t->waves == 8 && (t->chunk_groups == 4 || t->chunk_groups == 8));
+    const bool ok = (t->waves == 8 || t->waves == 16) && (t->chunk_groups == 4 || t->chunk_groups == 8);
     if (!ok) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: unsupported shape");
     plan->d.tuning.waves = t->waves;
     plan->d.tuning.chunk_groups = t->chunk_groups;

@@ -1,0 +1,145 @@
+"""GPU parity of the batched persistent decoder, the per-stream baseline, HIP
+graph replays, the autotuner and every launch shape of the single-stream kernel.
+
+Expected outputs are the seeded input symbols of every stream (lossless codec);
+comparisons are bit-exact.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_12141_amd as m
+    return m
+
+
+def _mixed_streams(rc, count=48, seed=77):
+    """Small streams covering the batch's variety: uint8/uint16, W 32/64, n 8..12,
+    single-symbol and tiny streams."""
+    out = []
+    for i in range(count):
+        spec = synth.mixed_stream_spec(seed, i, 1 << 10, 1 << 19, 4 << 10)
+        s = spec.generate()
+        lanes = 64 if i % 5 == 4 else 32
+        present = int(np.count_nonzero(np.bincount(s, minlength=spec.alphabet)))
+        n = max(spec.quant_bits, int(np.ceil(np.log2(max(present, 2)))))
+        if i == 7:
+            s = np.full(5000, 3, dtype=spec.dtype)         # one symbol only
+        if i == 11:
+            s = s[:20]                                      # fewer symbols than lanes
+        blob = rc.encode(s, lanes=lanes, quant_bits=n, splits=spec.splits, alphabet=spec.alphabet)
+        out.append((s, blob))
+    return out
+
+
+@pytest.fixture(scope="module")
+def mixed(rc):
+    return _mixed_streams(rc)
+
+
+def _check_all(batch, out, streams):
+    for i, (s, _) in enumerate(streams):
+        got = batch.symbols_of(out, i, s.dtype)
+        assert np.array_equal(got, s), f"stream {i}"
+
+
+def test_batch_persistent_and_per_stream(rc, mixed):
+    from paper_2306_12141_amd.batch import Batch
+    batch = Batch([b for _, b in mixed])
+    _say("batch items", batch.items, "ws", batch.workspace_bytes)
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    out.fill_(0xEE)
+    batch.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, mixed)
+    out.fill_(0x11)
+    batch.decode_per_stream(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, mixed)
+
+
+@pytest.mark.parametrize("shape", [(16, 4, 1), (16, 4, 2), (8, 4, 4), (8, 8, 1), (8, 8, 8), (16, 8, 2)])
+def test_batch_shapes(rc, mixed, shape):
+    from paper_2306_12141_amd._lib import Tuning
+    from paper_2306_12141_amd.batch import Batch
+    batch = Batch([b for _, b in mixed], Tuning(shape[0], shape[1], shape[2], 0))
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    out.fill_(0x5A)
+    batch.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, mixed)
+
+
+def test_graph_replays(rc, mixed):
+    """The captured graph replays several times, with eager work in between;
+    each replay must equal the eager result."""
+    from paper_2306_12141_amd.batch import Batch
+    batch = Batch([b for _, b in mixed])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    torch.cuda.synchronize()
+    g = batch.graph(ws, out, err)
+    for r in range(4):
+        out.fill_(r)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        _check_all(batch, out, mixed)
+        junk = torch.ones(1 << 20, device="cuda").sum()       # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+
+
+def test_autotune(rc, mixed):
+    from paper_2306_12141_amd.batch import Batch
+    batch = Batch([b for _, b in mixed])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    best, ms = batch.autotune(ws, out, err, reps=2)
+    _say("autotune", best.waves, best.chunk_groups, best.pairs_per_wave, ms)
+    out.fill_(0x33)
+    batch.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, mixed)
+
+
+@pytest.mark.parametrize("shape", [(16, 4), (8, 4), (8, 8), (16, 8)])
+@pytest.mark.parametrize("lanes,dt", [(32, np.uint8), (64, np.uint8), (32, np.uint16), (64, np.uint16)])
+def test_single_stream_shapes(rc, shape, lanes, dt):
+    A = 256 if dt == np.uint8 else 4096
+    s = synth.draw_symbols(synth.zipf_pmf(A, 1.1), 5 + lanes, 150_001, dt)
+    blob = rc.encode(s, lanes=lanes, quant_bits=12, splits=40, alphabet=A)
+    plan = rc.Plan(blob)
+    plan.set_tuning(waves=shape[0], chunk_groups=shape[1])
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    out.fill_(0x77)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    assert np.array_equal(plan.symbols_of(out), s)
