@@ -12,7 +12,18 @@ Also reported: the same stream at W = 64, the stream combined down to 16384 /
 kernel's roofline position, and the CPU oracle timed on the host cores on a
 bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c3|c4]
+Other workloads (each prints its own JSON line):
+  --workload c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8
+      and uint16, n 10..12, about 8 KiB per split) decoded by one hipGraph replay
+      of the persistent batched kernel (autotuned launch shape) versus one
+      single-stream launch per stream; value = batched decoded GB/s.
+  --workload c4: serving loop, Poisson arrivals at 2000 requests/s over a resident
+      corpus of 64 KiB..64 MiB streams stored with about 1 KiB per split; each
+      request asks for a log-uniform number of decode units (combined at
+      admission); 32 GiB request budget; value = sustained decoded GB/s, with
+      p50/p99/p99.9 latency from arrival to observed completion.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c3|c4]
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
 
@@ -175,6 +186,212 @@ def run_combined(args, base, torch, np, rc):
     return rows
 
 
+def _neff(spec, s, np):
+    """Quantisation bits able to code every present symbol: max(n, ceil(log2 #present))."""
+    present = int(np.count_nonzero(np.bincount(s, minlength=spec.alphabet)))
+    return max(spec.quant_bits, int(np.ceil(np.log2(max(present, 2)))))
+
+
+def _encode_specs(specs, rc, np, label):
+    """Generate and encode every stream (threads: generation and encoding release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
+
+    def one(spec):
+        s = spec.generate()
+        n = _neff(spec, s, np)
+        blob = rc.encode(s, lanes=spec.lanes, quant_bits=n, splits=spec.splits, alphabet=spec.alphabet)
+        return s, blob
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(one, specs))
+    total = sum(x[0].nbytes for x in res)
+    log(f"{label}: generated and encoded {len(res)} streams, {total / 2**30:.2f} GiB, "
+        f"in {time.perf_counter() - t0:.1f}s on {workers} threads")
+    return res
+
+
+def _time_launches(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    return sum(per) / len(per), per[len(per) // 2]
+
+
+def run_c3(args, torch, np, rc, synth):
+    from paper_2306_12141_amd.batch import Batch
+    specs = synth.c3_specs(args.c3_streams)
+    streams = _encode_specs(specs, rc, np, "C3")
+    blobs = [b for _, b in streams]
+    out_bytes = sum(s.nbytes for s, _ in streams)
+    words_bytes = sum(2 * b.info.n_words for b in blobs)
+    meta_bytes = sum(b.info.metadata_bytes for b in blobs)
+    batch = Batch(blobs)
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    torch.cuda.synchronize()
+    log(f"C3: {batch.items} work items, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
+    best, best_ms = batch.autotune(ws, out, err, reps=3)
+    shape = {"waves": best.waves, "chunk_groups": best.chunk_groups, "pairs_per_wave": best.pairs_per_wave}
+    log(f"C3: autotuned {shape} ({best_ms:.3f} ms)")
+    graph = batch.graph(ws, out, err)
+    stream = torch.cuda.current_stream()
+    g_mean, g_med = _time_launches(lambda: graph.launch(stream), args.steps, args.warmup, torch)
+    host = out.cpu().numpy()
+    exact_batched = int(err.item()) == 0
+    for i, (s, _) in enumerate(streams):
+        off, n = batch.output_range(i)
+        exact_batched &= bool(np.array_equal(host[off:off + n].view(s.dtype), s))
+    out.fill_(0)
+    ps_steps = max(3, args.steps // 4)
+    p_mean, p_med = _time_launches(lambda: batch.decode_per_stream(ws, out, err), ps_steps, 1, torch)
+    host = out.cpu().numpy()
+    exact_ps = int(err.item()) == 0
+    for i, (s, _) in enumerate(streams):
+        off, n = batch.output_range(i)
+        exact_ps &= bool(np.array_equal(host[off:off + n].view(s.dtype), s))
+    del host
+    value = out_bytes / (g_mean * 1e-3) / 1e9
+    per_stream = out_bytes / (p_mean * 1e-3) / 1e9
+    log(f"C3: batched {value:.1f} GB/s ({g_mean:.3f} ms), per-stream {per_stream:.1f} GB/s ({p_mean:.3f} ms), "
+        f"exact {exact_batched}/{exact_ps}")
+    alg = out_bytes + words_bytes + sum(b.info.splits * (16 + 4 * b.info.lanes) for b in blobs)
+    achieved = alg / (g_mean * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(g_mean, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded mixed streams; the paper's corpora are not available)",
+        "config": {"workload": f"{len(streams)} mixed streams, 4 KiB-16 MiB log-uniform, Laplace/Zipf/uniform, "
+                               f"3/4 uint8 (A=256) 1/4 uint16 (A=4096), n 10-12, W=32, ~8 KiB per split; "
+                               f"one hipGraph replay of the persistent batched kernel",
+                   "streams": len(streams), "decoded_bytes": out_bytes, "words_bytes": words_bytes,
+                   "metadata_bytes": meta_bytes, "work_items": batch.items, "tuning": shape,
+                   "bit_exact": exact_batched and exact_ps},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "decode_batch",
+                     "alg_bytes_per_launch": alg, "kernel_ms_mean": round(g_mean, 5)},
+        "cpu_baseline": None,
+        "extras": {"per_stream": {"decoded_gbs": round(per_stream, 3), "ms": round(p_mean, 5),
+                                  "ms_median": round(p_med, 5), "launches": len(streams)},
+                   "batched_ms_median": round(g_med, 5), "speedup_vs_per_stream": round(p_mean / g_mean, 3),
+                   "autotune_best_ms": round(best_ms, 4)},
+    }
+
+
+def run_c4(args, torch, np, rc, synth):
+    import threading
+    from paper_2306_12141_amd.server import Server, now_ns
+    specs = synth.c4_corpus_specs(args.c4_corpus)
+    corpus = _encode_specs(specs, rc, np, "C4 corpus")
+    resident = sum(2 * b.info.n_words + (64 << 10) for _, b in corpus)
+    resident = (resident + 255) // 256 * 256
+    budget = 32 << 30
+    hip_streams, max_batch, items = 4, 256, 1 << 17
+    ctrl = ((256 + 2 * ((max_batch * 4 + 255) // 256 * 256) + (max_batch * 64 + 255) // 256 * 256 + items * 16)
+            + 255) // 256 * 256
+    arena = torch.empty(resident + hip_streams * ctrl + budget, dtype=torch.uint8, device="cuda")
+    srv = Server(arena, resident, hip_streams=hip_streams, max_batch=max_batch, prep_threads=8,
+                 items_per_launch=items)
+    ids = [srv.add_content(b) for _, b in corpus]
+    splits_of = [b.info.splits for _, b in corpus]
+    rate, warm, dur = args.c4_rate, args.c4_warmup, args.c4_seconds
+    n_req = int(rate * (warm + dur))
+    arrivals = synth.poisson_arrivals(rate, n_req, seed=4)
+    n_req = int(np.searchsorted(arrivals, warm + dur))
+    pick = (synth.splitmix64(0xC4C4, 0, n_req) % np.uint64(len(ids))).astype(np.int64)
+    want = [synth.log_uniform_int(0x5D1, i, 1, splits_of[pick[i]]) for i in range(n_req)]
+    verify_every = 97
+    rec = {}
+    errors = []
+    done_evt = threading.Event()
+
+    def poller():
+        got = 0
+        while got < n_req:
+            for c in srv.poll(timeout_us=1000):
+                got += 1
+                rec[c.tag] = (c.t_arrival_ns, c.t_admit_ns, c.t_launch_ns, c.t_done_ns, c.out_bytes, c.status,
+                              c.device_error, c.splits)
+                if c.status == 0:
+                    if c.tag % verify_every == 0:
+                        s = corpus[c.content][0]
+                        if not np.array_equal(srv.output_of(c, s.dtype), s):
+                            errors.append(c.tag)
+                    srv.release(c.request_id)
+            if done_evt.is_set() and got < n_req and time.time() > deadline[0]:
+                break
+
+    deadline = [float("inf")]
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    t0 = now_ns() + 20_000_000
+    late = 0
+    for i in range(n_req):
+        due = t0 + int(arrivals[i] * 1e9)
+        while True:
+            d = due - now_ns()
+            if d <= 0:
+                break
+            if d > 300_000:
+                time.sleep((d - 200_000) * 1e-9)
+        if now_ns() - due > 1_000_000:
+            late += 1
+        srv.submit(ids[pick[i]], want[i], tag=i, arrival_ns=due)
+    done_evt.set()
+    deadline[0] = time.time() + 120
+    th.join()
+    st = srv.stats()
+    srv.close()
+    lat, win_bytes = [], 0
+    t_win0, t_win1 = t0 + int(warm * 1e9), t0 + int((warm + dur) * 1e9)
+    bad = 0
+    last_done = t_win0
+    for tag, (ta, tad, tl, td, ob, status, derr, spl) in rec.items():
+        if status != 0 or derr != 0:
+            bad += 1
+            continue
+        if ta >= t_win0:
+            lat.append((td - ta) * 1e-6)
+            win_bytes += ob
+            last_done = max(last_done, td)
+    lat = np.array(sorted(lat))
+    span = max(t_win1, last_done) - t_win0
+    sustained = win_bytes / (span * 1e-9) / 1e9
+    offered = float(np.mean([corpus[pick[i]][0].nbytes for i in range(n_req)])) * rate / 1e9
+    q = (lambda p: round(float(np.percentile(lat, p)), 3)) if len(lat) else (lambda p: None)
+    log(f"C4: {len(rec)}/{n_req} completed, window {len(lat)} requests, p50 {q(50)} ms, p99 {q(99)} ms, "
+        f"sustained {sustained:.2f} GB/s (offered {offered:.2f}), late submits {late}, bad {bad}, "
+        f"verify errors {len(errors)}")
+    return {
+        "metric": METRIC, "value": round(sustained, 3), "unit": "GB/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": int(warm * rate), "ms_per_step": q(50), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic (seeded corpus and Poisson arrivals; the paper's corpora are not available)",
+        "config": {"workload": f"serving: Poisson {rate:g} req/s over a resident corpus of {len(corpus)} streams "
+                               f"(64 KiB-64 MiB, C3 mix, ~1 KiB per stored split), per-request split count "
+                               f"log-uniform in [1, stored], combined at admission, 32 GiB budget, "
+                               f"{hip_streams} HIP streams, up to {max_batch} requests per launch",
+                   "requests": n_req, "window_s": dur, "warmup_s": warm,
+                   "bit_exact": not errors and bad == 0, "verified_requests": n_req // verify_every + 1},
+        "roofline": None,
+        "cpu_baseline": None,
+        "extras": {"latency_ms": {"p50": q(50), "p90": q(90), "p99": q(99), "p99.9": q(99.9),
+                                  "max": round(float(lat[-1]), 3) if len(lat) else None},
+                   "offered_gbs": round(offered, 3), "launches": st.launches,
+                   "requests_per_launch": round(st.requests_launched / max(1, st.launches), 2),
+                   "budget_peak_bytes": st.budget_peak, "late_submits": late, "failed": bad},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,7 +400,12 @@ def main():
     ap.add_argument("--lanes", type=int, default=32, choices=(32, 64))
     ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU",
                     help="launch shape of the decode kernel (default 16,4,0)")
-    ap.add_argument("--workload", default="c1", choices=("c1",))
+    ap.add_argument("--workload", default="c1", choices=("c1", "c3", "c4"))
+    ap.add_argument("--c3-streams", type=int, default=4096, help="streams in the batched workload")
+    ap.add_argument("--c4-corpus", type=int, default=128, help="resident streams in the serving corpus")
+    ap.add_argument("--c4-rate", type=float, default=2000.0, help="request arrival rate (1/s)")
+    ap.add_argument("--c4-seconds", type=float, default=30.0, help="measured window after warm-up (s)")
+    ap.add_argument("--c4-warmup", type=float, default=5.0, help="warm-up before the window (s)")
     ap.add_argument("--no-extras", action="store_true", help="skip the W=64 and combined-split runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="symbols in the oracle's sample")
@@ -202,6 +424,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload in ("c3", "c4"):
+        fn = run_c3 if args.workload == "c3" else run_c4
+        print(json.dumps(fn(args, torch, np, rc, synth)), flush=True)
+        return
     if args.copy_calibration:
         # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
         # the decode kernel's counters to bytes.

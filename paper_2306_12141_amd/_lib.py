@@ -93,3 +93,30 @@ recoil_batch_graph_create = _sig("recoil_batch_graph_create", [P, P, P, P, C.POI
 recoil_graph_launch = _sig("recoil_graph_launch", [P, P])
 recoil_graph_free = _sig("recoil_graph_free", [P], None)
 recoil_autotune = _sig("recoil_autotune", [P, P, P, P, P, u32, C.POINTER(Tuning), C.POINTER(C.c_float)])
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hip_streams", u32), ("max_batch", u32), ("prep_threads", u32), ("items_per_launch", u32),
+                ("resident_bytes", u64), ("tuning", Tuning)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("request_id", u64), ("tag", u64), ("content", u32), ("splits", u32), ("status", i32),
+                ("device_error", u32), ("out_offset", u64), ("out_bytes", u64), ("metadata_bytes", u64),
+                ("t_arrival_ns", u64), ("t_admit_ns", u64), ("t_launch_ns", u64), ("t_done_ns", u64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, u64) for n in ("submitted", "completed", "rejected", "launches", "requests_launched",
+                                   "pending", "in_flight", "budget_bytes", "budget_used", "budget_peak",
+                                   "resident_used", "decoded_bytes")]
+
+
+recoil_server_now_ns = _sig("recoil_server_now_ns", [], u64)
+recoil_server_create = _sig("recoil_server_create", [C.POINTER(ServerConfig), P, sz, C.POINTER(P)])
+recoil_server_add_content = _sig("recoil_server_add_content", [P, P, C.POINTER(u32)])
+recoil_server_submit = _sig("recoil_server_submit", [P, u32, u32, u64, u64, C.POINTER(u64)])
+recoil_server_poll = _sig("recoil_server_poll", [P, C.POINTER(Completion), u32, u32], u32)
+recoil_server_release = _sig("recoil_server_release", [P, u64])
+recoil_server_get_stats = _sig("recoil_server_get_stats", [P, C.POINTER(ServerStats)])
+recoil_server_destroy = _sig("recoil_server_destroy", [P], None)

@@ -34,7 +34,7 @@ def _compile(src: str) -> str:
 
 
 def sources():
-    return [s for s in HOST_SOURCES + DEVICE_SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    return HOST_SOURCES + DEVICE_SOURCES
 
 
 def build(verbose: bool = False) -> str:

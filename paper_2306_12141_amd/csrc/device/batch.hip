@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
         p.meta = reinterpret_cast<const UnitMeta *>(bp.ws + d.meta_off);
         p.lanes = reinterpret_cast<const uint32_t *>(bp.ws + d.lanes_off);
         p.out = bp.out + d.out_off;
-        p.err = bp.err;
+        p.err = bp.err + wi.stream * bp.err_stride;
         p.n_symbols = d.n_symbols;
         p.units = d.units;
         p.quant_bits = d.quant_bits;
@@ -75,7 +75,21 @@ __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
             if (d.symbol_bytes == 1) run_item<64, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
             else run_item<64, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
         }
-        __syncthreads();   // every wave is done with this table before the next item may replace it
+        if (bp.remaining) {
+            // Publish the stream's completion once its last item is done: every
+            // thread's stores reach device scope before the count drops, and the
+            // finishing workgroup makes them system-visible before the flag.
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0 && atomicSub(bp.remaining + wi.stream, 1u) == 1u) {
+                __threadfence_system();
+                const uint32_t e = __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(bp.host_done + wi.stream, kHostDone | e, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        } else {
+            __syncthreads();   // every wave is done with this table before the next item may replace it
+        }
     }
 }
 

@@ -36,10 +36,17 @@ struct BatchParams {
     const StreamDesc *streams;
     const WorkItem *items;
     uint32_t *head;               // work-queue head (device counter, reset before each launch)
-    uint32_t *err;
+    uint32_t *err;                // error word(s): err[stream * err_stride]
     uint32_t n_items;
     uint32_t lut_bytes;           // LDS bytes reserved for the largest table in the batch
+    uint32_t err_stride;          // 0: one error word for the launch; 1: one per stream
+    // Per-stream completion (both NULL to disable): remaining[s] counts the
+    // stream's items not yet finished; the workgroup that finishes the last one
+    // stores kHostDone | error bits to host_done[s] (host-visible memory).
+    uint32_t *remaining;
+    uint32_t *host_done;
 };
+constexpr uint32_t kHostDone = 0x80000000u;
 
 struct BatchTuning {
     uint32_t waves;       // waves per workgroup: 8 or 16

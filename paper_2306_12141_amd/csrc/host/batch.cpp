@@ -186,7 +186,7 @@ recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t 
         const PlanData &pl = b.plans[i];
         const StreamDesc &d = b.descs[i];
         if (pl.blob->n_words())
-            e = hipMemcpyAsync(base + d.words_off, pl.blob->words.data(), 2 * pl.blob->n_words(), hipMemcpyHostToDevice, stream);
+            e = hipMemcpyAsync(base + d.words_off, pl.blob->words(), 2 * pl.blob->n_words(), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(base + d.lut_off, pl.lut.data(), pl.lut.size(), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && !pl.meta.empty())
             e = hipMemcpyAsync(base + d.meta_off, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), hipMemcpyHostToDevice, stream);

@@ -24,7 +24,9 @@ struct BlobData {
     uint64_t n_symbols = 0;
     std::vector<uint32_t> freq;          // f[s], sums to 2^n
     std::vector<uint32_t> final_states;  // W
-    std::vector<uint16_t> words;         // B, written forward, read backward
+    // B words, written forward, read backward; shared between a blob and the
+    // blobs combined from it (the bitstream is the same, only split points differ).
+    std::shared_ptr<std::vector<uint16_t>> words_buf = std::make_shared<std::vector<uint16_t>>();
     // Split points k = 1..M-1 (index k-1), increasing word position.
     std::vector<uint64_t> sp_next;       // p_k + 1: words available to the unit starting there
     std::vector<uint64_t> sp_anchor;     // g_k: largest symbol group among the recorded lanes (0-based)
@@ -36,9 +38,10 @@ struct BlobData {
 
     uint32_t splits() const { return (uint32_t)sp_next.size() + 1; }
     uint64_t groups() const { return (n_symbols + lanes - 1) / lanes; }
-    uint64_t n_words() const { return words.size(); }
+    const uint16_t *words() const { return words_buf->data(); }
+    uint64_t n_words() const { return words_buf->size(); }
     uint64_t total_bytes() const {
-        return 48 + table_bits.size() + 4ull * lanes + meta_bits.size() + 2ull * words.size();
+        return 48 + table_bits.size() + 4ull * lanes + meta_bits.size() + 2ull * n_words();
     }
     // Symbol index recorded for lane j at split point k (1-based k).
     uint64_t split_index(uint32_t k, uint32_t j) const {
@@ -49,6 +52,9 @@ struct BlobData {
 
 // Fill table_bits / meta_bits; false if a value does not fit its series.
 bool pack_sections(BlobData &b);
+// Keep every ceil(M / target)-th split point (Sec. 3.3); the bitstream is shared,
+// not copied. nullptr if the re-packed metadata does not fit its series.
+std::shared_ptr<BlobData> combine_data(const BlobData &a, uint32_t target);
 
 void set_error(const std::string &msg);
 recoil_status fail(recoil_status s, const std::string &msg);

@@ -289,8 +289,9 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads) {
     const bool want_splits = threads > 1;
     uint32_t x[64];
     for (uint32_t j = 0; j < W; ++j) x[j] = kLower;
+    std::vector<uint16_t> &words = *b.words_buf;
     // Words per symbol are at most one (b >= n); reserve an estimate.
-    b.words.reserve((size_t)(b.n_symbols / 2) + 16);
+    words.reserve((size_t)(b.n_symbols / 2) + 16);
     const uint32_t shift = kLowerBits + kWordBits - n;   // threshold = ((L >> n) << b) * f
     uint32_t j = 0;
     for (uint64_t i = 0; i < b.n_symbols; ++i) {
@@ -299,10 +300,10 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads) {
         uint32_t xs = x[j];
         if ((uint64_t)xs >= ((uint64_t)fs << shift)) {
             // Emit the low word first, then shift (Eq. 3).
-            b.words.push_back((uint16_t)(xs & 0xFFFFu));
+            words.push_back((uint16_t)(xs & 0xFFFFu));
             xs >>= kWordBits;
             if (want_splits)
-                chooser.event(b.words.size() - 1, (int64_t)i - (int64_t)W, xs);
+                chooser.event(words.size() - 1, (int64_t)i - (int64_t)W, xs);
         }
         x[j] = ((xs / fs) << n) + F[s] + (xs % fs);     // Eq. 1
         if (++j == W) j = 0;
@@ -431,24 +432,32 @@ recoil_status encode(const void *symbols, uint64_t N, const recoil_config *cfg, 
     return RECOIL_OK;
 }
 
-recoil_status combine(const recoil_blob *in, uint32_t target, recoil_blob **out) {
-    if (!in || !out || target < 1) return fail(RECOIL_ERR_INVALID_ARG, "combine: bad arguments");
-    *out = nullptr;
-    const BlobData &a = *in->data;
+std::shared_ptr<BlobData> combine_data(const BlobData &a, uint32_t target) {
     const uint32_t M = a.splits();
-    const uint32_t step = (uint32_t)cdiv(M, std::min(target, M));
+    const uint32_t step = (uint32_t)cdiv(M, std::min(std::max(target, 1u), M));
     auto b = std::make_shared<BlobData>();
     b->lanes = a.lanes; b->quant_bits = a.quant_bits; b->symbol_bytes = a.symbol_bytes;
     b->alphabet = a.alphabet; b->n_symbols = a.n_symbols;
-    b->freq = a.freq; b->final_states = a.final_states; b->words = a.words;
+    b->freq = a.freq; b->final_states = a.final_states; b->words_buf = a.words_buf;
     const uint64_t W = a.lanes;
+    const size_t kept = M / step;
+    b->sp_next.reserve(kept); b->sp_anchor.reserve(kept);
+    b->sp_state.reserve(kept * W); b->sp_gdiff.reserve(kept * W);
     for (uint64_t k = step; k < M; k += step) {
         b->sp_next.push_back(a.sp_next[k - 1]);
         b->sp_anchor.push_back(a.sp_anchor[k - 1]);
         b->sp_state.insert(b->sp_state.end(), a.sp_state.begin() + (k - 1) * W, a.sp_state.begin() + k * W);
         b->sp_gdiff.insert(b->sp_gdiff.end(), a.sp_gdiff.begin() + (k - 1) * W, a.sp_gdiff.begin() + k * W);
     }
-    if (!pack_sections(*b)) return fail(RECOIL_ERR_INFEASIBLE, "combine: metadata does not fit its series");
+    if (!pack_sections(*b)) return nullptr;
+    return b;
+}
+
+recoil_status combine(const recoil_blob *in, uint32_t target, recoil_blob **out) {
+    if (!in || !out || target < 1) return fail(RECOIL_ERR_INVALID_ARG, "combine: bad arguments");
+    *out = nullptr;
+    std::shared_ptr<BlobData> b = combine_data(*in->data, target);
+    if (!b) return fail(RECOIL_ERR_INFEASIBLE, "combine: metadata does not fit its series");
     auto *h = new (std::nothrow) recoil_blob();
     if (!h) return fail(RECOIL_ERR_INVALID_ARG, "combine: out of memory");
     h->data = std::move(b);
@@ -471,7 +480,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     h.push_back((uint8_t)kLowerBits); h.push_back((uint8_t)kWordBits); h.push_back(0);
     put_u(h, b.alphabet, 4);
     put_u(h, b.n_symbols, 8);
-    put_u(h, b.words.size(), 8);
+    put_u(h, b.n_words(), 8);
     put_u(h, b.splits(), 4);
     put_u(h, b.table_bits.size(), 4);
     put_u(h, b.meta_bits.size(), 4);
@@ -484,7 +493,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     for (uint32_t x : b.final_states) { for (int k = 0; k < 4; ++k) *p++ = (uint8_t)(x >> (8 * k)); }
     std::memcpy(p, b.meta_bits.data(), b.meta_bits.size());
     p += b.meta_bits.size();
-    for (uint16_t w : b.words) { *p++ = (uint8_t)w; *p++ = (uint8_t)(w >> 8); }
+    for (uint16_t w : *b.words_buf) { *p++ = (uint8_t)w; *p++ = (uint8_t)(w >> 8); }
     return RECOIL_OK;
 }
 
@@ -581,8 +590,9 @@ recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
         return fail(RECOIL_ERR_CORRUPT, "container: metadata present with one split");
     }
     q += mbytes;
-    b->words.resize(B);
-    for (uint64_t k = 0; k < B; ++k) b->words[k] = (uint16_t)(q[2 * k] | (q[2 * k + 1] << 8));
+    std::vector<uint16_t> &words = *b->words_buf;
+    words.resize(B);
+    for (uint64_t k = 0; k < B; ++k) words[k] = (uint16_t)(q[2 * k] | (q[2 * k + 1] << 8));
     if (!pack_sections(*b)) return fail(RECOIL_ERR_CORRUPT, "container: does not re-pack");
     if (b->table_bits.size() != tbytes || b->meta_bits.size() != mbytes)
         return fail(RECOIL_ERR_CORRUPT, "container: non-canonical series widths");
@@ -641,7 +651,7 @@ recoil_status recoil_blob_info(const recoil_blob *blob, recoil_blob_info_t *out)
     if (!blob || !out) return recoil::fail(RECOIL_ERR_INVALID_ARG, "blob_info: bad arguments");
     const recoil::BlobData &b = *blob->data;
     out->n_symbols = b.n_symbols;
-    out->n_words = b.words.size();
+    out->n_words = b.n_words();
     out->splits = b.splits();
     out->lanes = b.lanes;
     out->quant_bits = b.quant_bits;

@@ -19,7 +19,7 @@ inline size_t align_up(size_t v) { return ws_align(v); }
 // top .. glo and stores ghi .. glo, where ghi is the group of its own
 // synchronisation completion point (all lanes switched on) and glo is one
 // above the previous unit's.
-recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
+recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
     const BlobData &b = *bp;
     const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
@@ -59,8 +59,12 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl
             prev_sync = m.ghi;
         }
     }
-    // Decode table.
-    const uint32_t slots = 1u << n;
+    return RECOIL_OK;
+}
+
+// Decode table: slot -> (symbol, f, slot - F) for the 2^n slots (Eq. 2).
+void build_table(const BlobData &b, PlanData &pl) {
+    const uint32_t slots = 1u << b.quant_bits;
     uint32_t present = 0, only = 0;
     for (uint32_t s = 0; s < b.alphabet; ++s)
         if (b.freq[s]) { ++present; only = s; }
@@ -84,8 +88,14 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl
         }
         F += f;
     }
+}
+
+recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
+    recoil_status st = build_units(bp, pl);
+    if (st) return st;
+    build_table(*bp, pl);
     size_t off = 0;
-    pl.off_words = off; off += words_section_bytes(b.n_words());
+    pl.off_words = off; off += words_section_bytes(bp->n_words());
     pl.off_lut = off;   off = align_up(off + pl.lut.size());
     pl.off_meta = off;  off = align_up(off + pl.meta.size() * sizeof(UnitMeta));
     pl.off_lanes = off; off = align_up(off + pl.lanes.size() * 4);
@@ -128,7 +138,7 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t byt
     char *base = static_cast<char *>(d_ws);
     const BlobData &b = *pl.blob;
     hipError_t e = hipSuccess;
-    if (b.n_words()) e = hipMemcpyAsync(base + pl.off_words, b.words.data(), 2 * b.n_words(), hipMemcpyHostToDevice, stream);
+    if (b.n_words()) e = hipMemcpyAsync(base + pl.off_words, b.words(), 2 * b.n_words(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lut, pl.lut.data(), pl.lut.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, hipMemcpyHostToDevice, stream);

@@ -27,6 +27,10 @@ inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAli
 
 // Unpack split metadata and build the decode table; fills the single-stream layout.
 recoil_status build_plan(const std::shared_ptr<const BlobData> &blob, PlanData &plan);
+// The two halves of build_plan: per-unit and per-lane records only (checks the
+// GPU limits and sets the default tuning), and the decode table only.
+recoil_status build_units(const std::shared_ptr<const BlobData> &blob, PlanData &plan);
+void build_table(const BlobData &blob, PlanData &plan);
 
 // Bytes of the words section for B words (padded so chunks can be fetched whole).
 inline size_t words_section_bytes(uint64_t n_words) { return ws_align(2 * (n_words + kChunkPadWords)); }

@@ -22,6 +22,8 @@ available here; the distributions below stand in for them:
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Dict, List
 
@@ -115,17 +117,35 @@ def _integer_cdf(pmf: np.ndarray) -> np.ndarray:
     return edges
 
 
-def draw_symbols(pmf: np.ndarray, seed: int, n: int, dtype, chunk: int = 1 << 24,
+def _workers() -> int:
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def draw_symbols(pmf: np.ndarray, seed: int, n: int, dtype, chunk: int = 1 << 22,
                  perm: np.ndarray | None = None) -> np.ndarray:
-    """n iid draws from pmf by inverse CDF on the top 32 bits of SplitMix64."""
+    """n iid draws from pmf by inverse CDF on the top 32 bits of SplitMix64.
+
+    Draw i depends only on (seed, i), so chunks are filled by parallel threads
+    (numpy releases the GIL) with the same result as a sequential loop.
+    """
     edges = _integer_cdf(pmf)
     out = np.empty(n, dtype=dtype)
     lut = None if perm is None else perm.astype(dtype)
-    for start in range(0, n, chunk):
+
+    def fill(start: int) -> None:
         cnt = min(chunk, n - start)
         u = splitmix64(seed, start, cnt) >> np.uint64(32)
         s = np.searchsorted(edges, u, side="right")
         out[start:start + cnt] = s if lut is None else lut[s]
+
+    starts = range(0, n, chunk)
+    if n <= chunk:
+        for st in starts:
+            fill(st)
+    else:
+        with ThreadPoolExecutor(max_workers=_workers()) as ex:
+            list(ex.map(fill, starts))
     return out
 
 
