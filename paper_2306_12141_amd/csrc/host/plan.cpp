@@ -62,6 +62,75 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     return RECOIL_OK;
 }
 
+namespace {
+inline uint32_t bit_length(uint64_t v) { return v ? 64u - (uint32_t)__builtin_clzll(v) : 0u; }
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return b ? (a + b - 1) / b : 0; }
+}  // namespace
+
+// The per-unit records of the blob obtained by combining `full` to `target`
+// units (every ceil(M/target)-th split point kept, Sec. 3.3), built in one pass
+// over the kept split points without materialising the combined blob.
+// *packed_bytes receives the size of that blob's packed metadata section (the
+// series of Sec. 4.3: signed offset and group series, then per split point W
+// 16-bit states and an unsigned group-difference series).
+recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, uint32_t target, PlanData &pl,
+                                   uint64_t *packed_bytes) {
+    const BlobData &b = *bp;
+    const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
+    if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
+    if (n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs n <= 12");
+    if (b.n_symbols >= (1ull << 32) || b.n_words() >= (1ull << 32))
+        return fail(RECOIL_ERR_UNSUPPORTED, "plan: N and B must be below 2^32");
+    const uint32_t step = (uint32_t)ceil_div(M, std::min(std::max(target, 1u), M));
+    const uint32_t Mc = (M - 1) / step + 1;
+    pl.blob = bp;
+    pl.tuning.waves = 16;
+    pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
+    pl.tuning.blocks_per_cu = 0;
+    const uint64_t G = b.groups();
+    pl.meta.resize(Mc);
+    pl.lanes.resize((size_t)Mc * W);
+    const uint64_t Eb = ceil_div(b.n_words(), Mc), Eg = ceil_div(G, Mc);
+    uint64_t max_o = 0, max_x = 0, bits = 0;
+    uint32_t prev_sync = 0;
+    for (uint32_t u = 0; u < Mc; ++u) {
+        UnitMeta &m = pl.meta[u];
+        m.glo = (u == 0) ? 0u : prev_sync + 1;
+        uint32_t *lanes = &pl.lanes[(size_t)u * W];
+        if (u + 1 == Mc) {
+            m.next = (uint32_t)b.n_words();
+            m.top = G ? (uint32_t)(G - 1) : 0u;
+            m.ghi = m.top;
+            for (uint32_t j = 0; j < W; ++j) lanes[j] = b.final_states[j];
+            continue;
+        }
+        const uint64_t k = (uint64_t)(u + 1) * step - 1;   // split point (u+1)*step, stored at index - 1
+        m.next = (uint32_t)b.sp_next[k];
+        m.top = (uint32_t)b.sp_anchor[k];
+        const uint16_t *st = &b.sp_state[k * W];
+        const uint16_t *gd = &b.sp_gdiff[k * W];
+        uint32_t maxdiff = 0;
+        for (uint32_t j = 0; j < W; ++j) {
+            maxdiff = std::max<uint32_t>(maxdiff, gd[j]);
+            lanes[j] = (uint32_t)st[j] | ((uint32_t)gd[j] << 16);
+        }
+        m.ghi = m.top - maxdiff;
+        prev_sync = m.ghi;
+        const int64_t o = (int64_t)b.sp_next[k] - (int64_t)((u + 1) * Eb);
+        const int64_t x = (int64_t)(b.sp_anchor[k] + 1) - (int64_t)((u + 1) * Eg);
+        max_o = std::max<uint64_t>(max_o, o < 0 ? (uint64_t)-o : (uint64_t)o);
+        max_x = std::max<uint64_t>(max_x, x < 0 ? (uint64_t)-x : (uint64_t)x);
+        bits += 16ull * W + 4 + (uint64_t)W * std::max<uint32_t>(1, bit_length(maxdiff));
+    }
+    if (Mc > 1) {
+        const uint32_t wo = std::max<uint32_t>(1, bit_length(max_o)), wx = std::max<uint32_t>(1, bit_length(max_x));
+        if (wo > 32 || wx > 32) return fail(RECOIL_ERR_INFEASIBLE, "combine: metadata does not fit its series");
+        bits += 2ull * 5 + (uint64_t)(Mc - 1) * (2 + wo + wx);
+    }
+    if (packed_bytes) *packed_bytes = (bits + 7) / 8;
+    return RECOIL_OK;
+}
+
 // Decode table: slot -> (symbol, f, slot - F) for the 2^n slots (Eq. 2).
 void build_table(const BlobData &b, PlanData &pl) {
     const uint32_t slots = 1u << b.quant_bits;

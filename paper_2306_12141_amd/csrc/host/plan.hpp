@@ -31,6 +31,10 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &blob, PlanData &
 // GPU limits and sets the default tuning), and the decode table only.
 recoil_status build_units(const std::shared_ptr<const BlobData> &blob, PlanData &plan);
 void build_table(const BlobData &blob, PlanData &plan);
+// Per-unit records of the blob that combining `blob` to `target` units would
+// give, without building that blob; *packed_bytes: its packed metadata size.
+recoil_status build_units_combined(const std::shared_ptr<const BlobData> &blob, uint32_t target, PlanData &plan,
+                                   uint64_t *packed_bytes);
 
 // Bytes of the words section for B words (padded so chunks can be fetched whole).
 inline size_t words_section_bytes(uint64_t n_words) { return ws_align(2 * (n_words + kChunkPadWords)); }

@@ -169,34 +169,27 @@ struct recoil_server {
 namespace recoil {
 namespace {
 
-// Combine the content's split metadata down to the requested count and build
-// the per-unit records (host work of one request, counted in its latency).
+// Combine the content's split metadata down to the requested count: the
+// per-unit records of the kept split points and the size of the metadata a
+// client would receive (host work of one request, counted in its latency).
 void prepare(Request &r) {
     const std::shared_ptr<const BlobData> &full = r.content.blob;
-    std::shared_ptr<const BlobData> b = full;
     const uint32_t M = full->splits();
-    if (r.splits_asked && r.splits_asked < M) {
-        std::shared_ptr<BlobData> cb = combine_data(*full, r.splits_asked);
-        if (!cb) {
-            r.c.status = RECOIL_ERR_INFEASIBLE;
-            r.ready.store(-1, std::memory_order_release);
-            return;
-        }
-        b = std::move(cb);
-    }
-    r.c.metadata_bytes = b->meta_bits.size();
-    recoil_status st = build_units(b, r.plan);
+    const uint32_t target = (r.splits_asked && r.splits_asked < M) ? r.splits_asked : M;
+    uint64_t packed = 0;
+    recoil_status st = build_units_combined(full, target, r.plan, &packed);
     if (st) {
         r.c.status = st;
         r.ready.store(-1, std::memory_order_release);
         return;
     }
-    const uint32_t Mc = b->splits();
+    r.c.metadata_bytes = packed;
+    const uint32_t Mc = (uint32_t)r.plan.meta.size();
     r.c.splits = Mc;
     r.c.out_bytes = full->n_symbols * full->symbol_bytes;
     r.unit_bytes = ws_align(Mc * sizeof(UnitMeta));
-    r.meta_bytes = r.unit_bytes + ws_align((uint64_t)Mc * b->lanes * 4);
-    r.pairs = b->lanes == 32 ? (Mc + 1) / 2 : Mc;
+    r.meta_bytes = r.unit_bytes + ws_align((uint64_t)Mc * full->lanes * 4);
+    r.pairs = full->lanes == 32 ? (Mc + 1) / 2 : Mc;
     r.ready.store(1, std::memory_order_release);
 }
 

@@ -101,8 +101,12 @@ def test_alone(rc, corpus):
                 got = _drain(srv, 1)
                 c = got[rid]
                 _check(srv, corpus, c)
-                full = corpus[cid][1].splits
+                blob = corpus[cid][1]
+                full = blob.splits
                 assert c.splits == (full if splits == 0 else _combined_units(full, splits))
+                # The size a client would receive equals the combined container's metadata section.
+                ref = blob if splits == 0 else blob.combine(splits)
+                assert c.metadata_bytes == ref.info.metadata_bytes
                 srv.release(rid)
         st = srv.stats()
         assert st.completed == 3 * len(ids) and st.budget_used == 0 and st.pending == 0
