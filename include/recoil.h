@@ -181,7 +181,8 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, siz
                                  hipStream_t stream);
 /* Size in bytes of the split metadata as uploaded (part of device_bytes). */
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
-/* Launch shape used by recoil_decode for this plan (default 16 waves, K = 4).
+/* Launch shape used by recoil_decode for this plan (default: 16 waves per
+ * workgroup; K = 8 groups per super-step for uint8 tables, 4 for uint16).
  * Errors: INVALID_ARG (unsupported shape). */
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *tuning);
 void recoil_plan_free(recoil_plan *plan);

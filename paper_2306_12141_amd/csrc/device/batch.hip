@@ -28,7 +28,8 @@ __device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ri
 }
 
 template <int K, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET), amdgpu_waves_per_eu(8, 8))) void decode_batch(
+    BatchParams bp) {
     using L = Lds<16, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
@@ -42,8 +43,8 @@ __global__ __launch_bounds__(64 * WAVES) void decode_batch(BatchParams bp) {
         __syncthreads();
         const uint32_t it = uni(lds_ld<uint32_t>(base));
         if (it >= bp.n_items) break;
-        const WorkItem wi = bp.items[it];
-        const StreamDesc d = bp.streams[wi.stream];
+        const WorkItem wi = uni_load(bp.items + it);
+        const StreamDesc d = uni_load(bp.streams + wi.stream);
         if ((int32_t)wi.stream != cur) {
             const uint32_t chunks = ((d.symbol_bytes == 1 ? 4u : 8u) << d.quant_bits) / 16;
             const uint4 *src = reinterpret_cast<const uint4 *>(bp.ws + d.lut_off);

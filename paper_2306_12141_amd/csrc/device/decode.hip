@@ -40,7 +40,8 @@ namespace {
 using namespace dev;
 
 template <int W, typename Sym, int K, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void decode_units(DecodeParams p) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET))) void decode_units(
+    DecodeParams p) {
     using D = PairDecoder<W, Sym, K>;
     using L = Lds<0, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -55,8 +56,19 @@ __global__ __launch_bounds__(64 * WAVES) void decode_units(DecodeParams p) {
     const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t npairs = (p.units + D::S - 1) / D::S;
+    const uint32_t first = blockIdx.x * WAVES + wave, stride = gridDim.x * WAVES;
     D d(p, base + L::TABLE, base + L::PAD + wave * L::WAVE_LDS, lane);
-    for (uint32_t pair = blockIdx.x * WAVES + wave; pair < npairs; pair += gridDim.x * WAVES) d.run(pair);
+    // Pairs are dealt out by position. The issue arbiter favours older waves,
+    // which would leave the youngest waves holding the last pairs of the launch
+    // alone (a shared work counter costs more: same-address atomics serialise).
+    // Instead each wave raises its priority the more of its share is left.
+    const uint32_t share = first < npairs ? (npairs - 1 - first) / stride + 1 : 0u;
+    uint32_t left = share;
+    for (uint32_t pair = first; pair < npairs; pair += stride) {
+        --left;
+        set_priority(4 * left / share);
+        d.run(pair);
+    }
 }
 
 template <typename Sym>

@@ -105,6 +105,35 @@ struct Lds {
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Wave issue priority 0..3 (larger values go first; the level is clamped).
+__device__ inline void set_priority(uint32_t level) {
+    if (level >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (level == 2) __builtin_amdgcn_s_setprio(2);
+    else if (level == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
+// A wave-uniform record read from global memory: every dword through
+// readfirstlane, so its fields live in SGPRs rather than in VGPR copies.
+template <typename T>
+__device__ inline T uni_load(const T *src) {
+    static_assert(sizeof(T) % 4 == 0, "record of whole dwords");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, src, sizeof(T));
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(T) / 4; ++i) w[i] = uni(w[i]);
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
+// Scalar registers per wave for the decode kernels. A SIMD held eight waves of
+// a kernel using 62 of them but only seven at 76 (measured per-wave start
+// times), and the decode loop needs every wave it can get to hide its LDS
+// latency, so the kernels are compiled to this budget (the few values that do
+// not fit are kept in a VGPR outside the group loops).
+#define RECOIL_SGPR_BUDGET 64
+
 template <int W, typename Sym, int K>
 struct PairDecoder {
     using G = Geo<W, K>;
@@ -119,11 +148,13 @@ struct PairDecoder {
     uint32_t lane_ring;    // this lane's chunk-slice address in the top third of its unit's ring
     uint32_t n, mask;
 
-    // Per unit of the pair (wave-uniform).
-    uint32_t valid[S], last[S], top[S], ghi[S], steps[S], sync[S];
+    // Per unit of the pair (wave-uniform). Kept few: the register file holds
+    // eight waves per SIMD only while a wave needs at most 64 scalar registers.
+    uint32_t top[S], ghi[S], steps[S];
     int32_t cur[S];        // words remaining: the next word to read is cur - 1
-    int32_t stop[S];       // ring slot of word cur - 1 (in [0, R))
+    uint32_t ua[S];        // LDS byte address of word cur - 1 in the unit's ring
     int32_t fq[S];         // lowest chunk held in the ring
+    uint32_t presync;      // leading groups of the pair that need the predicated body
     // Per lane.
     uint32_t x, rec, act;
     bool active;
@@ -197,27 +228,31 @@ struct PairDecoder {
     __device__ bool begin(uint32_t pair) {
         const uint32_t u0 = pair * S;
         bool any = false;
+        uint32_t sync_max = 0;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             const uint32_t u = u0 + h;
-            valid[h] = u < p.units;
-            last[h] = valid[h] && u + 1 == p.units;
+            const bool valid = u < p.units;
+            const bool last = valid && u + 1 == p.units;
             UnitMeta m = {0, 0, 0, 1};
-            if (valid[h]) m = p.meta[u];
+            if (valid) m = p.meta[u];
             cur[h] = (int32_t)uni(m.next);
             top[h] = uni(m.top);
             ghi[h] = uni(m.ghi);
             const uint32_t glo = uni(m.glo);
-            steps[h] = (valid[h] && top[h] + 1 > glo) ? top[h] + 1 - glo : 0u;
-            if (last[h]) sync[h] = (p.n_symbols % W) ? 1u : 0u;
-            else sync[h] = valid[h] ? top[h] - ghi[h] + 1 : 0u;
+            steps[h] = (valid && top[h] + 1 > glo) ? top[h] + 1 - glo : 0u;
+            uint32_t sync = valid ? top[h] - ghi[h] + 1 : 0u;
+            if (last) sync = (p.n_symbols % W) ? 1u : 0u;
+            sync_max = max(sync_max, sync);
             any = any || steps[h] > 0;
         }
-        const uint32_t my_valid = pick(valid, upper);
-        const uint32_t my_last = pick(last, upper);
-        rec = my_valid ? p.lanes[(uint64_t)(u0 + upper) * W + coder] : 0u;
+        presync = sync_max;
+        const uint32_t mine = u0 + upper;
+        const bool my_valid = mine < p.units;
+        const bool my_last = my_valid && mine + 1 == p.units;
+        rec = my_valid ? p.lanes[(uint64_t)mine * W + coder] : 0u;
         x = my_last ? rec : 0u;
-        active = my_last != 0;
+        active = my_last;
         act = my_last ? 0u : (rec >> 16);
         // Initial fill: the chunk holding word cur-1 and the two below it.
         int32_t q0[S];
@@ -225,7 +260,7 @@ struct PairDecoder {
         for (uint32_t h = 0; h < S; ++h) {
             q0[h] = cur[h] > 0 ? (cur[h] - 1) / (int32_t)C : -1;
             fq[h] = q0[h] >= 2 ? q0[h] - 2 : 0;
-            stop[h] = cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0;
+            ua[h] = uni(ring_addr(h, cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0));
         }
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
@@ -233,29 +268,29 @@ struct PairDecoder {
         return any;
     }
 
-    // One group's read step. ua (and e, for unit B when W = 32) is the LDS
+    // One group's read step. a (and e, for unit B when W = 32) is the LDS
     // address of the unit's next word to read; need is this lane's "x < L" (and live).
     template <uint32_t G_IDX>
-    __device__ inline void read_step(bool need, uint32_t &ua, uint32_t &e) {
+    __device__ inline void read_step(bool need, uint32_t &a, uint32_t &e) {
         const uint64_t bal = __ballot(need);
         const uint32_t bl = (uint32_t)bal, bh = (uint32_t)(bal >> 32);
         const uint32_t m = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl, 0u));
         // The lane's word is m words above the unit's top word (descending ring).
-        // ua/e stay opaque SGPR byte addresses so each address is one v_lshl_add.
-        asm volatile("" : "+s"(ua));
+        // a/e stay opaque SGPR byte addresses so each address is one v_lshl_add.
+        asm volatile("" : "+s"(a));
         if constexpr (W == 32) asm volatile("" : "+s"(e));
         uint32_t addr;
         if constexpr (W == 64) {
-            addr = (m << 1) + ua;
-            ua += 2u * (uint32_t)__builtin_popcountll(bal);
+            addr = (m << 1) + a;
+            a += 2u * (uint32_t)__builtin_popcountll(bal);
         } else {
             // Upper lanes' m also counts unit A's readers; unit A's advance cancels them.
-            const uint32_t ua_next = ua + 2u * (uint32_t)__builtin_popcount(bl);
-            const uint32_t d = e - ua_next;                         // e is unit B's top address
-            uint32_t t = (m << 1) + ua;
+            const uint32_t a_next = a + 2u * (uint32_t)__builtin_popcount(bl);
+            const uint32_t d = e - a_next;                         // e is unit B's top address
+            uint32_t t = (m << 1) + a;
             asm volatile("" : "+v"(t));                             // keep v_lshl_add + v_mad_u32_u24
             addr = __umul24(upper, d) + t;
-            ua = ua_next;
+            a = a_next;
             e += 2u * (uint32_t)__builtin_popcount(bh);
         }
         uint32_t w = lds_ld<uint16_t>(addr);
@@ -264,42 +299,32 @@ struct PairDecoder {
         x = need ? ((x << 16) | w) : x;
     }
 
-    // Super-step start: LDS address of each unit's top word.
-    __device__ inline void step_bases(uint32_t &ua, uint32_t &e) const {
-        ua = uni(ring_addr(0, stop[0]));
-        if constexpr (S == 2) e = uni(ring_addr(1, stop[1]));
-        else e = 0;
-    }
-
-    // Super-step end: words consumed per unit from the top-address advance.
-    __device__ inline void step_advance(uint32_t ua0, uint32_t ua, uint32_t e0, uint32_t e) {
-        const int32_t ca = (int32_t)((ua - ua0) >> 1);
-        cur[0] -= ca;
-        stop[0] -= ca;
-        if (stop[0] < 0) stop[0] += (int32_t)R;
+    // Super-step end: words consumed per unit from the top-address advance; an
+    // address that moved into the mirror (below slot 0) wraps to the ring's top.
+    __device__ inline void step_advance(uint32_t a_end, uint32_t e_end) {
+        cur[0] -= (int32_t)((a_end - ua[0]) >> 1);
+        ua[0] = a_end >= ring_addr(0, -1) ? a_end - 2 * R : a_end;
         if constexpr (S == 2) {
-            const int32_t cb = (int32_t)((e - e0) >> 1);
-            cur[1] -= cb;
-            stop[1] -= cb;
-            if (stop[1] < 0) stop[1] += (int32_t)R;
+            cur[1] -= (int32_t)((e_end - ua[1]) >> 1);
+            ua[1] = e_end >= ring_addr(1, -1) ? e_end - 2 * R : e_end;
         }
     }
 
     template <uint32_t G_IDX>
-    __device__ inline void group_fast(uint32_t &ua, uint32_t &e, unsigned char *outh, uint32_t lane_off) {
-        read_step<G_IDX>(x < kL, ua, e);
+    __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh, uint32_t lane_off) {
+        read_step<G_IDX>(x < kL, a, e);
         const uint32_t s = T::step(lut, x, n, mask);
         *reinterpret_cast<Sym *>(outh + lane_off - G_IDX * W * sizeof(Sym)) = (Sym)s;
     }
 
     template <uint32_t G_IDX>
-    __device__ inline void group_pred(uint32_t k, uint32_t &ua, uint32_t &e) {
+    __device__ inline void group_pred(uint32_t k, uint32_t &a, uint32_t &e) {
         const bool live = k < pick(steps, upper);
         if (live && !active && k == act) {
             active = true;
             x = rec & 0xFFFFu;
         }
-        read_step<G_IDX>(live && active && x < kL, ua, e);
+        read_step<G_IDX>(live && active && x < kL, a, e);
         const uint32_t h = pick(top, upper) - k;
         const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
@@ -309,84 +334,77 @@ struct PairDecoder {
     }
 
     template <bool PRED, uint32_t... G_IDX>
-    __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &ua, uint32_t &e,
+    __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &a, uint32_t &e,
                                   unsigned char *outh, uint32_t lane_off) {
-        if constexpr (PRED) (group_pred<G_IDX>(k + G_IDX, ua, e), ...);
-        else (group_fast<G_IDX>(ua, e, outh, lane_off), ...);
+        if constexpr (PRED) (group_pred<G_IDX>(k + G_IDX, a, e), ...);
+        else (group_fast<G_IDX>(a, e, outh, lane_off), ...);
     }
 
+    // The K groups of a super-step (the unpredicated body stores through a
+    // uniform group pointer plus a fixed per-lane offset).
     template <bool PRED>
-    __device__ inline bool super_step(uint32_t k) {
-        // Prefetch the next chunk of any unit with fewer than 2C words resident.
-        bool ld[S];
-#pragma unroll
-        for (uint32_t h = 0; h < S; ++h)
-            ld[h] = steps[h] > k && fq[h] > 0 && cur[h] - fq[h] * (int32_t)C < 2 * (int32_t)C;
-        // Each unit's lanes fetch their own slice with a scalar base; one register
-        // set suffices because the two units of a pair use disjoint lanes.
-        // One load instruction for the whole wave (each unit's lanes address their
-        // own chunk), issued whenever any unit needs one. Its registers are not
-        // touched again before the end of the super-step, so the load overlaps
-        // the K groups; a conditional or split load would make the compiler copy
-        // the destination, and a copy waits (vmcnt) for the load and the stores.
-        bool any_ld = false;
-#pragma unroll
-        for (uint32_t h = 0; h < S; ++h) any_ld = any_ld || ld[h];
-        Chunk pre;
-        if (any_ld) {
-            const uint32_t qa = (uint32_t)max(fq[0] - 1, 0);
-            uint64_t off = (uint64_t)qa * (2 * C);
-            if constexpr (S == 2) {
-                const uint32_t qb = (uint32_t)max(fq[1] - 1, 0);
-                off = upper ? (uint64_t)qb * (2 * C) : off;
-            }
-            pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) + off +
-                                                   col * (uint32_t)sizeof(Chunk));
-        }
-        uint32_t ua, e;
-        step_bases(ua, e);
-        const uint32_t ua0 = ua, e0 = e;
+    __device__ inline void step_groups(uint32_t k, uint32_t &a, uint32_t &e) {
         unsigned char *outh = nullptr;
         uint32_t lane_off = 0;
         if constexpr (!PRED) {
-            // Unit A's group pointer is uniform; each lane's offset from it is fixed.
             outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top[0] - k) * W * sizeof(Sym);
             lane_off = coder;
             if constexpr (S == 2) lane_off += upper * W * (top[1] - top[0]);
             lane_off *= sizeof(Sym);
         }
-        groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, ua, e, outh, lane_off);
-        step_advance(ua0, ua, e0, e);
-        // The fetched chunks are consumed only here, K groups after their
-        // request: the empty asm keeps the scheduler from hoisting their use
-        // (and its wait on the load) into the groups above.
-        if (any_ld) {
+        groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e, outh, lane_off);
+    }
+
+    template <bool PRED>
+    __device__ inline bool super_step(uint32_t k) {
+        // Units with fewer than 2C words resident fetch their next chunk (bit h).
+        uint32_t ld = 0;
+#pragma unroll
+        for (uint32_t h = 0; h < S; ++h)
+            if (steps[h] > k && fq[h] > 0 && cur[h] - fq[h] * (int32_t)C < 2 * (int32_t)C) ld |= 1u << h;
+        uint32_t a = ua[0], e = S == 2 ? ua[S - 1] : 0u;
+        if (ld) {
+            // One load for the whole wave, each unit's lanes addressing their own
+            // chunk by a 32-bit byte offset from the scalar bitstream base. The
+            // registers stay untouched until the K groups are done, so the load
+            // overlaps them; the empty asm keeps the scheduler from hoisting the
+            // chunk's use (and its wait on the load) into the groups.
+            uint32_t off = (uint32_t)max(fq[0] - 1, 0) * (2 * C);
+            if constexpr (S == 2) {
+                const uint32_t off_b = (uint32_t)max(fq[1] - 1, 0) * (2 * C);
+                off = upper ? off_b : off;
+            }
+            Chunk pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) +
+                                                         (off + col * (uint32_t)sizeof(Chunk)));
+            step_groups<PRED>(k, a, e);
             asm volatile("" : "+v"(pre));
 #pragma unroll
             for (uint32_t h = 0; h < S; ++h)
-                if (ld[h] && (S == 1 || upper == h)) put_chunk(fq[h] - 1, pre, lane_ring);
+                if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(fq[h] - 1, pre, lane_ring);
+        } else {
+            step_groups<PRED>(k, a, e);
         }
+        step_advance(a, e);
         bool ok = true;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
-            if (ld[h]) fq[h] -= 1;
+            fq[h] -= (int32_t)((ld >> h) & 1u);
             // The unit bookkeeping is wave-uniform; say so, so it stays in SGPRs.
             fq[h] = (int32_t)uni((uint32_t)fq[h]);
             cur[h] = (int32_t)uni((uint32_t)cur[h]);
-            stop[h] = (int32_t)uni((uint32_t)stop[h]);
-            if (valid[h] && cur[h] < 0) ok = false;   // read below the first word: corrupt split data
+            ua[h] = uni(ua[h]);
+            if (cur[h] < 0) ok = false;   // read below the first word: corrupt split data
         }
         return ok;
     }
 
     __device__ void run(uint32_t pair) {
         if (!begin(pair)) return;
-        uint32_t kmax = 0, kmin = 0xFFFFFFFFu, presync = 0;
+        uint32_t kmax = 0, kmin = 0xFFFFFFFFu;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             kmax = max(kmax, steps[h]);
             kmin = min(kmin, steps[h]);
-            presync = max(presync, sync[h]);
         }
         for (uint32_t k = 0; k < kmax; k += K) {
             const bool pred = k < presync || k + K > kmin;

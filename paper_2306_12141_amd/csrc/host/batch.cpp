@@ -28,6 +28,10 @@ struct BatchData {
 
 namespace {
 
+// Head section of the batch workspace: the work-queue head, reset by a kernel
+// before each persistent launch.
+constexpr size_t kBatchHeadBytes = 256;
+
 uint32_t pairs_of(const PlanData &pl) {
     const uint32_t W = pl.blob->lanes, M = pl.blob->splits();
     return W == 32 ? (M + 1) / 2 : M;
@@ -115,7 +119,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     for (const PlanData &pl : b.plans) cap += pl.single_symbol ? 1 : (pairs_of(pl) + 7) / 8;
     b.items_cap = std::max<size_t>(cap, 1);
     size_t off = 0;
-    b.off_head = off;  off = ws_align(off + 4);
+    b.off_head = off;  off = ws_align(off + kBatchHeadBytes);
     b.off_descs = off; off = ws_align(off + count * sizeof(StreamDesc));
     b.off_items = off; off = ws_align(off + b.items_cap * sizeof(WorkItem));
     b.descs.resize(count);
@@ -180,8 +184,11 @@ recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t 
     if (bytes < b.total_ws) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "batch_upload: workspace too small");
     if (reinterpret_cast<uintptr_t>(d_ws) % kWsAlign) return fail(RECOIL_ERR_ALIGNMENT, "batch_upload: workspace not 256-byte aligned");
     char *base = static_cast<char *>(d_ws);
-    hipError_t e = hipMemcpyAsync(base + b.off_descs, b.descs.data(), b.descs.size() * sizeof(StreamDesc),
-                                  hipMemcpyHostToDevice, stream);
+    static const uint8_t zero_head[kBatchHeadBytes] = {};
+    hipError_t e = hipMemcpyAsync(base + b.off_head, zero_head, kBatchHeadBytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + b.off_descs, b.descs.data(), b.descs.size() * sizeof(StreamDesc),
+                           hipMemcpyHostToDevice, stream);
     for (size_t i = 0; e == hipSuccess && i < b.plans.size(); ++i) {
         const PlanData &pl = b.plans[i];
         const StreamDesc &d = b.descs[i];

@@ -63,7 +63,8 @@ def _server(rc, corpus, budget_bytes, hip_streams=2, max_batch=256, items_per_la
     region + one control region per stream + budget)."""
     from paper_2306_12141_amd.server import Server
     resident = _align(sum(b.info.n_words * 2 + (64 << 10) for _, b in corpus))
-    ctrl = _align(512 + _align(max_batch * 64) + items_per_launch * 16)
+    # Control region per stream: queue head, error words, item counts, descriptors, items.
+    ctrl = _align(256 + 2 * _align(max_batch * 4) + _align(max_batch * 64) + items_per_launch * 16)
     arena = torch.empty(resident + hip_streams * ctrl + _align(budget_bytes), dtype=torch.uint8, device="cuda")
     srv = Server(arena, resident, hip_streams=hip_streams, max_batch=max_batch,
                  items_per_launch=items_per_launch)
