@@ -105,6 +105,14 @@ struct Lds {
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// (x << 1) + y on the scalar unit in one instruction; the compiler emits a
+// shift and an add for it.
+__device__ inline uint32_t s_lshl1_add(uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("s_lshl1_add_u32 %0, %1, %2" : "=s"(r) : "s"(x), "s"(y) : "scc");
+    return r;
+}
+
 // Wave issue priority 0..3 (larger values go first; the level is clamped).
 __device__ inline void set_priority(uint32_t level) {
     if (level >= 3) __builtin_amdgcn_s_setprio(3);
@@ -143,20 +151,23 @@ struct PairDecoder {
 
     const DecodeParams &p;
     uint32_t lut;          // LDS address of the decode table
-    uint32_t ring0;        // LDS address of this wave's first unit (mirror start)
+    uint32_t ring0;        // LDS address of this wave's first unit
     uint32_t lane, col, upper, coder;
     uint32_t lane_ring;    // this lane's chunk-slice address in the top third of its unit's ring
     uint32_t n, mask;
 
     // Per unit of the pair (wave-uniform). Kept few: the register file holds
     // eight waves per SIMD only while a wave needs at most 64 scalar registers.
-    uint32_t top[S], ghi[S], steps[S];
-    int32_t cur[S];        // words remaining: the next word to read is cur - 1
-    uint32_t ua[S];        // LDS byte address of word cur - 1 in the unit's ring
-    int32_t fq[S];         // lowest chunk held in the ring
+    uint32_t top0;         // unit 0's first group (the fast body's store base)
+    uint32_t steps[S];     // groups the unit decodes
+    int32_t res[S];        // words of the unit still in the ring: (next word + 1) - fq * C
+    uint32_t ua[S];        // LDS byte address of the unit's next word in its ring
+    int32_t fq[S];         // lowest chunk held in the ring (the next fetch is fq - 1)
+    uint32_t po[S];        // byte offset from the top third of the third that chunk fq - 1 goes to
     uint32_t presync;      // leading groups of the pair that need the predicated body
     // Per lane.
     uint32_t x, rec, act;
+    uint32_t my_top, my_ghi, my_steps, lane_off;
     bool active;
 
     __device__ PairDecoder(const DecodeParams &p_, uint32_t lut_, uint32_t ring0_, uint32_t lane_)
@@ -169,12 +180,6 @@ struct PairDecoder {
         lane_ring = lane_ring_addr();
     }
 
-    template <typename V>
-    __device__ static inline V pick(const V (&a)[S], uint32_t h) {
-        if constexpr (S == 1) return a[0];
-        else return h ? a[1] : a[0];
-    }
-
     // LDS byte address of ring position s (s in [-C, R)) of unit h. The ring is
     // stored in descending order (slot R-1 lowest, the mirror of slots 2C..3C-1
     // above slot 0), so consecutive reads of a group go upwards in LDS.
@@ -182,17 +187,19 @@ struct PairDecoder {
         return ring0 + h * G::UNIT + 2u * (uint32_t)((int32_t)R - 1 - s);
     }
 
+    // Byte offset, from the top third, of the third holding chunk q.
+    __device__ static inline uint32_t third_off(int32_t q) { return 2u * C * (uint32_t)(2 - q % 3); }
+
     // This lane's slice of chunk q (uniform q): a scalar base plus a fixed lane offset.
     __device__ inline Chunk fetch(int32_t q) const {
         const unsigned char *base = reinterpret_cast<const unsigned char *>(p.words) + (uint64_t)(uint32_t)q * (2 * C);
         return *reinterpret_cast<const Chunk *>(base + col * (uint32_t)sizeof(Chunk));
     }
 
-    // This lane's slice (K words, ascending) into the ring of its unit with the
-    // words reversed, for chunk q (uniform). lane_ring is the lane's slice
-    // address for chunks in the top third; the other thirds and the mirror are
-    // fixed offsets from it, chosen by the scalar q mod 3.
-    __device__ inline void put_chunk(int32_t q, const Chunk &v, uint32_t lane_ring) {
+    // This lane's slice (K words, ascending) of a chunk into the ring third at
+    // byte offset off from the top third, words reversed; the top third is also
+    // written to the mirror below slot 0.
+    __device__ inline void put_chunk(uint32_t off, const Chunk &v) {
         Chunk r16;
         if constexpr (K == 4) {
             r16.x = __builtin_amdgcn_alignbit(v.y, v.y, 16);
@@ -203,32 +210,19 @@ struct PairDecoder {
             r16.z = __builtin_amdgcn_alignbit(v.y, v.y, 16);
             r16.w = __builtin_amdgcn_alignbit(v.x, v.x, 16);
         }
-        const int32_t r = q % 3;
-        if (r == 2) {
-            lds_st<Chunk>(lane_ring, r16);
-            lds_st<Chunk>(lane_ring + 6 * C, r16);     // mirror, below slot 0
-        } else if (r == 1) {
-            lds_st<Chunk>(lane_ring + 2 * C, r16);
-        } else {
-            lds_st<Chunk>(lane_ring + 4 * C, r16);
-        }
+        lds_st<Chunk>(lane_ring + off, r16);
+        if (off == 0) lds_st<Chunk>(lane_ring + 6 * C, r16);
     }
 
     // Lane slice address for chunks in the top third of the ring.
     __device__ inline uint32_t lane_ring_addr() const { return ring_addr(upper, 2 * (int32_t)C + (int32_t)(K * col + K - 1)); }
 
-    // Chunk q of unit h into the ring: only the lanes of unit h take part.
-    __device__ inline void load_put(uint32_t h, int32_t q, uint32_t lane_ring) {
-        if (S == 1 || upper == h) {
-            const Chunk v = fetch(q);
-            put_chunk(q, v, lane_ring);
-        }
-    }
-
     __device__ bool begin(uint32_t pair) {
         const uint32_t u0 = pair * S;
         bool any = false;
         uint32_t sync_max = 0;
+        int32_t cur[S];
+        uint32_t top[S], ghi[S];
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             const uint32_t u = u0 + h;
@@ -247,6 +241,12 @@ struct PairDecoder {
             any = any || steps[h] > 0;
         }
         presync = sync_max;
+        top0 = top[0];
+        my_top = S == 2 && upper ? top[S - 1] : top[0];
+        my_ghi = S == 2 && upper ? ghi[S - 1] : ghi[0];
+        my_steps = S == 2 && upper ? steps[S - 1] : steps[0];
+        // Fast-body store offset of this lane from unit 0's group pointer.
+        lane_off = (coder + (S == 2 ? upper * W * (my_top - top0) : 0u)) * (uint32_t)sizeof(Sym);
         const uint32_t mine = u0 + upper;
         const bool my_valid = mine < p.units;
         const bool my_last = my_valid && mine + 1 == p.units;
@@ -260,11 +260,14 @@ struct PairDecoder {
         for (uint32_t h = 0; h < S; ++h) {
             q0[h] = cur[h] > 0 ? (cur[h] - 1) / (int32_t)C : -1;
             fq[h] = q0[h] >= 2 ? q0[h] - 2 : 0;
+            res[h] = cur[h] - fq[h] * (int32_t)C;
             ua[h] = uni(ring_addr(h, cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0));
+            po[h] = third_off(fq[h] + 2);      // chunk fq - 1 shares a third with fq + 2
         }
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
-            for (int32_t q = q0[h]; q >= 0 && q > q0[h] - 3; --q) load_put(h, q, lane_ring);
+            for (int32_t q = q0[h]; q >= 0 && q > q0[h] - 3; --q)
+                if (S == 1 || upper == h) put_chunk(third_off(q), fetch(q));
         return any;
     }
 
@@ -282,10 +285,10 @@ struct PairDecoder {
         uint32_t addr;
         if constexpr (W == 64) {
             addr = (m << 1) + a;
-            a += 2u * (uint32_t)__builtin_popcountll(bal);
+            a = s_lshl1_add((uint32_t)__builtin_popcountll(bal), a);
         } else {
             // Upper lanes' m also counts unit A's readers; unit A's advance cancels them.
-            const uint32_t a_next = a + 2u * (uint32_t)__builtin_popcount(bl);
+            const uint32_t a_next = s_lshl1_add((uint32_t)__builtin_popcount(bl), a);
             const uint32_t d = e - a_next;                         // e is unit B's top address
             uint32_t t = (m << 1) + a;
             asm volatile("" : "+v"(t));                             // keep v_lshl_add + v_mad_u32_u24
@@ -299,19 +302,8 @@ struct PairDecoder {
         x = need ? ((x << 16) | w) : x;
     }
 
-    // Super-step end: words consumed per unit from the top-address advance; an
-    // address that moved into the mirror (below slot 0) wraps to the ring's top.
-    __device__ inline void step_advance(uint32_t a_end, uint32_t e_end) {
-        cur[0] -= (int32_t)((a_end - ua[0]) >> 1);
-        ua[0] = a_end >= ring_addr(0, -1) ? a_end - 2 * R : a_end;
-        if constexpr (S == 2) {
-            cur[1] -= (int32_t)((e_end - ua[1]) >> 1);
-            ua[1] = e_end >= ring_addr(1, -1) ? e_end - 2 * R : e_end;
-        }
-    }
-
     template <uint32_t G_IDX>
-    __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh, uint32_t lane_off) {
+    __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh) {
         read_step<G_IDX>(x < kL, a, e);
         const uint32_t s = T::step(lut, x, n, mask);
         *reinterpret_cast<Sym *>(outh + lane_off - G_IDX * W * sizeof(Sym)) = (Sym)s;
@@ -319,56 +311,49 @@ struct PairDecoder {
 
     template <uint32_t G_IDX>
     __device__ inline void group_pred(uint32_t k, uint32_t &a, uint32_t &e) {
-        const bool live = k < pick(steps, upper);
+        const bool live = k < my_steps;
         if (live && !active && k == act) {
             active = true;
             x = rec & 0xFFFFu;
         }
         read_step<G_IDX>(live && active && x < kL, a, e);
-        const uint32_t h = pick(top, upper) - k;
+        const uint32_t h = my_top - k;
         const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
             const uint32_t s = T::step(lut, x, n, mask);
-            if (h <= pick(ghi, upper)) static_cast<Sym *>(p.out)[i] = (Sym)s;
+            if (h <= my_ghi) static_cast<Sym *>(p.out)[i] = (Sym)s;
         }
     }
 
     template <bool PRED, uint32_t... G_IDX>
-    __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &a, uint32_t &e,
-                                  unsigned char *outh, uint32_t lane_off) {
-        if constexpr (PRED) (group_pred<G_IDX>(k + G_IDX, a, e), ...);
-        else (group_fast<G_IDX>(a, e, outh, lane_off), ...);
-    }
-
-    // The K groups of a super-step (the unpredicated body stores through a
-    // uniform group pointer plus a fixed per-lane offset).
-    template <bool PRED>
-    __device__ inline void step_groups(uint32_t k, uint32_t &a, uint32_t &e) {
-        unsigned char *outh = nullptr;
-        uint32_t lane_off = 0;
-        if constexpr (!PRED) {
-            outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top[0] - k) * W * sizeof(Sym);
-            lane_off = coder;
-            if constexpr (S == 2) lane_off += upper * W * (top[1] - top[0]);
-            lane_off *= sizeof(Sym);
+    __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &a, uint32_t &e) {
+        if constexpr (PRED) {
+            (group_pred<G_IDX>(k + G_IDX, a, e), ...);
+        } else {
+            unsigned char *outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top0 - k) * W * sizeof(Sym);
+            (group_fast<G_IDX>(a, e, outh), ...);
         }
-        groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e, outh, lane_off);
     }
 
+    // K groups. At the start, every unit with fewer than 2C words resident
+    // requests its next chunk into registers; the chunk is written to the ring
+    // after the K groups, so the load overlaps them. (Every step consumes at
+    // most C words, so a unit keeps at least C words resident, and reads stay
+    // within the ring plus its mirror.) Returns false if a unit read past its
+    // first word (corrupt split data).
     template <bool PRED>
     __device__ inline bool super_step(uint32_t k) {
-        // Units with fewer than 2C words resident fetch their next chunk (bit h).
         uint32_t ld = 0;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
-            if (steps[h] > k && fq[h] > 0 && cur[h] - fq[h] * (int32_t)C < 2 * (int32_t)C) ld |= 1u << h;
+            if ((!PRED || steps[h] > k) && fq[h] > 0 && res[h] < 2 * (int32_t)C) ld |= 1u << h;
         uint32_t a = ua[0], e = S == 2 ? ua[S - 1] : 0u;
         if (ld) {
             // One load for the whole wave, each unit's lanes addressing their own
             // chunk by a 32-bit byte offset from the scalar bitstream base. The
-            // registers stay untouched until the K groups are done, so the load
-            // overlaps them; the empty asm keeps the scheduler from hoisting the
-            // chunk's use (and its wait on the load) into the groups.
+            // registers stay untouched until the K groups are done; the empty asm
+            // keeps the scheduler from hoisting the chunk's use (and its wait on
+            // the load) into the groups.
             uint32_t off = (uint32_t)max(fq[0] - 1, 0) * (2 * C);
             if constexpr (S == 2) {
                 const uint32_t off_b = (uint32_t)max(fq[1] - 1, 0) * (2 * C);
@@ -376,24 +361,29 @@ struct PairDecoder {
             }
             Chunk pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) +
                                                          (off + col * (uint32_t)sizeof(Chunk)));
-            step_groups<PRED>(k, a, e);
+            groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e);
             asm volatile("" : "+v"(pre));
 #pragma unroll
             for (uint32_t h = 0; h < S; ++h)
-                if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(fq[h] - 1, pre, lane_ring);
+                if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(po[h], pre);
         } else {
-            step_groups<PRED>(k, a, e);
+            groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e);
         }
-        step_advance(a, e);
         bool ok = true;
+        uint32_t a_end = a;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
-            fq[h] -= (int32_t)((ld >> h) & 1u);
-            // The unit bookkeeping is wave-uniform; say so, so it stays in SGPRs.
-            fq[h] = (int32_t)uni((uint32_t)fq[h]);
-            cur[h] = (int32_t)uni((uint32_t)cur[h]);
-            ua[h] = uni(ua[h]);
-            if (cur[h] < 0) ok = false;   // read below the first word: corrupt split data
+            if (h == 1) a_end = e;
+            // Words consumed from the top-address advance; an address that moved
+            // into the mirror (below slot 0) wraps to the ring's top.
+            res[h] -= (int32_t)((a_end - ua[h]) >> 1);
+            ua[h] = a_end >= ring_addr(h, -1) ? a_end - 2 * R : a_end;
+            if ((ld >> h) & 1u) {
+                fq[h] -= 1;
+                res[h] += (int32_t)C;
+                po[h] = po[h] == 4 * C ? 0u : po[h] + 2 * C;
+            }
+            if (res[h] < 0) ok = false;   // read below the first word: corrupt split data
         }
         return ok;
     }
@@ -406,14 +396,14 @@ struct PairDecoder {
             kmax = max(kmax, steps[h]);
             kmin = min(kmin, steps[h]);
         }
-        for (uint32_t k = 0; k < kmax; k += K) {
-            const bool pred = k < presync || k + K > kmin;
-            const bool ok = pred ? super_step<true>(k) : super_step<false>(k);
-            if (!ok) {
-                if (lane == 0) atomicOr(p.err, kDevErrUnderflow);
-                return;
-            }
-        }
+        // Predicated while synchronising, unpredicated while every unit has K
+        // more groups, predicated for the rest.
+        bool ok = true;
+        uint32_t k = 0;
+        for (; ok && k < kmax && k < presync; k += K) ok = super_step<true>(k);
+        for (; ok && k + K <= kmin; k += K) ok = super_step<false>(k);
+        for (; ok && k < kmax; k += K) ok = super_step<true>(k);
+        if (!ok && lane == 0) atomicOr(p.err, kDevErrUnderflow);
     }
 };
 
