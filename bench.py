@@ -49,7 +49,8 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_2306_12141_amd/csrc/device/decode.hip", "paper_2306_12141_amd/csrc/device/decode.hpp"):
+    for rel in ("paper_2306_12141_amd/csrc/device/decode.hip", "paper_2306_12141_amd/csrc/device/decode.hpp",
+                "paper_2306_12141_amd/csrc/device/decode_core.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
