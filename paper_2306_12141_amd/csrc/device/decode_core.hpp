@@ -159,6 +159,7 @@ struct PairDecoder {
     // Per unit of the pair (wave-uniform). Kept few: the register file holds
     // eight waves per SIMD only while a wave needs at most 64 scalar registers.
     uint32_t top0;         // unit 0's first group (the fast body's store base)
+    uint32_t top_min;      // smallest first group of the pair's units
     uint32_t steps[S];     // groups the unit decodes
     int32_t res[S];        // words of the unit still in the ring: (next word + 1) - fq * C
     uint32_t ua[S];        // LDS byte address of the unit's next word in its ring
@@ -242,6 +243,7 @@ struct PairDecoder {
         }
         presync = sync_max;
         top0 = top[0];
+        top_min = S == 2 ? min(top[0], top[S - 1]) : top[0];
         my_top = S == 2 && upper ? top[S - 1] : top[0];
         my_ghi = S == 2 && upper ? ghi[S - 1] : ghi[0];
         my_steps = S == 2 && upper ? steps[S - 1] : steps[0];
@@ -341,7 +343,7 @@ struct PairDecoder {
     // most C words, so a unit keeps at least C words resident, and reads stay
     // within the ring plus its mirror.) Returns false if a unit read past its
     // first word (corrupt split data).
-    template <bool PRED>
+    template <bool PRED, uint32_t KK = K>
     __device__ inline bool super_step(uint32_t k) {
         uint32_t ld = 0;
 #pragma unroll
@@ -361,13 +363,13 @@ struct PairDecoder {
             }
             Chunk pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) +
                                                          (off + col * (uint32_t)sizeof(Chunk)));
-            groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e);
+            groups<PRED>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
             asm volatile("" : "+v"(pre));
 #pragma unroll
             for (uint32_t h = 0; h < S; ++h)
                 if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(po[h], pre);
         } else {
-            groups<PRED>(std::make_integer_sequence<uint32_t, K>{}, k, a, e);
+            groups<PRED>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
         }
         bool ok = true;
         uint32_t a_end = a;
@@ -396,13 +398,30 @@ struct PairDecoder {
             kmax = max(kmax, steps[h]);
             kmin = min(kmin, steps[h]);
         }
-        // Predicated while synchronising, unpredicated while every unit has K
-        // more groups, predicated for the rest.
+        // Synchronisation runs predicated, in half super-steps so that little
+        // of the pair does.
         bool ok = true;
         uint32_t k = 0;
-        for (; ok && k < kmax && k < presync; k += K) ok = super_step<true>(k);
-        for (; ok && k + K <= kmin; k += K) ok = super_step<false>(k);
-        for (; ok && k < kmax; k += K) ok = super_step<true>(k);
+        for (; ok && k < kmax && k < presync; k += K / 2) ok = super_step<true, K / 2>(k);
+        // From here every state of every unit is exact, so a unit that has
+        // decoded its own groups may run on into the groups below: it stores
+        // there the symbols the unit below stores too, and reads that unit's
+        // words. The rest of the pair then runs unpredicated in whole super-steps,
+        // provided every unit is still within its own groups here (a unit that
+        // ended during synchronisation stopped advancing) and running on reaches
+        // neither below group 0 nor below word 0 (the first units of the stream);
+        // otherwise the end runs predicated.
+        const uint32_t kend = k < kmax ? k + (kmax - k + K - 1) / K * K : k;
+        bool run_on = k <= kmin && top_min + 1 >= kend;
+#pragma unroll
+        for (uint32_t h = 0; h < S; ++h)
+            run_on = run_on && res[h] + fq[h] * (int32_t)C >= (int32_t)((kend - k) * W);
+        if (run_on) {
+            for (; ok && k < kmax; k += K) ok = super_step<false>(k);
+        } else {
+            for (; ok && k + K <= kmin; k += K) ok = super_step<false>(k);
+            for (; ok && k < kmax; k += K) ok = super_step<true>(k);
+        }
         if (!ok && lane == 0) atomicOr(p.err, kDevErrUnderflow);
     }
 };
