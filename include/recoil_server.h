@@ -20,10 +20,14 @@
  * entry points are thread-safe. The launcher polls its events while launches are
  * in flight, so it keeps one host core busy under load.
  *
- * Requests are admitted strictly in submission order: a request that does not fit
- * waits (and holds back later ones) until outputs are released or launches finish.
- * A request that cannot fit even in an empty budget completes with
- * RECOIL_ERR_BUFFER_TOO_SMALL.
+ * Requests are admitted in submission order within two classes. A "long" request
+ * (few decode units for its size: more than long_unit_bytes of output per unit)
+ * decodes serially for a long time, and a launch keeps its stream until its
+ * slowest request ends, so launches holding long requests may occupy at most
+ * long_streams of the streams; short requests pass waiting long ones. A request
+ * that does not fit the budget waits (and holds back later ones) until outputs
+ * are released or launches finish; one that cannot fit even in an empty budget
+ * completes with RECOIL_ERR_BUFFER_TOO_SMALL.
  */
 #ifndef RECOIL_SERVER_H
 #define RECOIL_SERVER_H
@@ -43,6 +47,9 @@ typedef struct {
     uint32_t items_per_launch;  /* work-item capacity of one launch, 1024..2^22 */
     uint64_t resident_bytes;    /* arena bytes at its start reserved for content */
     recoil_tuning tuning;       /* launch shape of the batched kernel (recoil_default_tuning()) */
+    uint64_t long_unit_bytes;   /* a request with more output bytes per decode unit is "long" (0: 131072) */
+    uint32_t long_streams;      /* most launches holding long requests in flight (0: hip_streams / 2, >= 1) */
+    uint32_t reserved;
 } recoil_server_config;
 
 typedef struct {

@@ -97,7 +97,8 @@ recoil_autotune = _sig("recoil_autotune", [P, P, P, P, P, u32, C.POINTER(Tuning)
 
 class ServerConfig(C.Structure):
     _fields_ = [("hip_streams", u32), ("max_batch", u32), ("prep_threads", u32), ("items_per_launch", u32),
-                ("resident_bytes", u64), ("tuning", Tuning)]
+                ("resident_bytes", u64), ("tuning", Tuning), ("long_unit_bytes", u64), ("long_streams", u32),
+                ("reserved", u32)]
 
 
 class Completion(C.Structure):

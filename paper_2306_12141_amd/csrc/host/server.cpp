@@ -94,12 +94,14 @@ struct Request {
     recoil_completion c{};
     Content content;
     uint32_t splits_asked = 0;
+    uint64_t long_unit_bytes = 0;
     PlanData plan;               // unit and lane records of the combined metadata
     uint64_t unit_bytes = 0;     // device bytes of the unit records (aligned)
     uint64_t meta_bytes = 0;     // unit + lane records (aligned)
     uint32_t pairs = 0;          // unit pairs (W = 32) or units (W = 64)
     uint32_t per_item = 0;       // pairs per work item in its launch
     uint32_t items = 0;          // work items in its launch
+    bool is_long = false;        // many output bytes per decode unit (serial for long)
     bool completed = false;      // completion published (launcher thread only)
     std::atomic<int> ready{0};   // 1: planned; -1: failed (c.status says why)
 };
@@ -130,6 +132,7 @@ struct Slot {
     uint64_t meta_off = 0, meta_bytes = 0;
     std::vector<RequestPtr> reqs;
     bool busy = false;
+    bool holds_long = false;            // the launch in flight carries a long request
 };
 
 }  // namespace
@@ -190,6 +193,7 @@ void prepare(Request &r) {
     r.unit_bytes = ws_align(Mc * sizeof(UnitMeta));
     r.meta_bytes = r.unit_bytes + ws_align((uint64_t)Mc * full->lanes * 4);
     r.pairs = full->lanes == 32 ? (Mc + 1) / 2 : Mc;
+    r.is_long = r.c.out_bytes > r.long_unit_bytes * (uint64_t)Mc;
     r.ready.store(1, std::memory_order_release);
 }
 
@@ -264,26 +268,26 @@ bool reap(recoil_server *s) {
     return any;
 }
 
-// Take the longest ready prefix of the queue that fits one launch and the
-// budget; called with s->mu held. Returns the admitted requests (may be empty).
-std::vector<RequestPtr> admit_locked(recoil_server *s, Slot &sl, bool idle) {
+// Take, in queue order, the ready requests that fit one launch and the budget,
+// passing over long ones when allow_long is false; called with s->mu held.
+// Returns the admitted requests (may be empty) and removes them from the queue.
+std::vector<RequestPtr> admit_locked(recoil_server *s, Slot &sl, bool idle, bool allow_long) {
     const uint32_t base_per_item = std::max(1u, s->cfg.tuning.waves * s->cfg.tuning.pairs_per_wave);
     std::vector<RequestPtr> take;
     uint64_t items = 0;
-    while (!s->pending.empty() && take.size() < s->cfg.max_batch) {
-        // Requests that failed planning complete at once, in queue order.
-        size_t i = take.size();
-        if (i >= s->pending.size()) break;
+    for (size_t i = 0; i < s->pending.size() && take.size() < s->cfg.max_batch;) {
         RequestPtr r = s->pending[i];
         const int rd = r->ready.load(std::memory_order_acquire);
         if (rd == 0) break;
         if (rd < 0) {
-            if (i != 0) break;
+            // Failed planning: complete at once.
             r->c.t_admit_ns = r->c.t_launch_ns = r->c.t_done_ns = clock_ns();
-            s->pending.pop_front();
+            s->pending.erase(s->pending.begin() + (ptrdiff_t)i);
             complete_locked(s, *r);
             continue;
         }
+        ++i;
+        if (r->is_long && !allow_long) continue;
         r->per_item = base_per_item;
         uint64_t n = items_of(*r, r->per_item);
         if (items + n > s->cfg.items_per_launch) {
@@ -309,22 +313,32 @@ std::vector<RequestPtr> admit_locked(recoil_server *s, Slot &sl, bool idle) {
     }
     take.resize(k);
     if (k == 0) {
-        // Nothing fits. If nothing else holds budget, the queue head never will.
+        // Nothing fits. If nothing else holds budget, this request never will.
         if (idle && s->budget.used() == 0) {
             RequestPtr r = s->pending.front();
-            s->pending.pop_front();
-            r->c.status = RECOIL_ERR_BUFFER_TOO_SMALL;
-            r->c.t_admit_ns = r->c.t_launch_ns = r->c.t_done_ns = clock_ns();
-            complete_locked(s, *r);
+            if (r->ready.load(std::memory_order_acquire) > 0 && (!r->is_long || allow_long)) {
+                s->pending.pop_front();
+                r->c.status = RECOIL_ERR_BUFFER_TOO_SMALL;
+                r->c.t_admit_ns = r->c.t_launch_ns = r->c.t_done_ns = clock_ns();
+                complete_locked(s, *r);
+            }
         }
         return take;
     }
     sl.meta_bytes = meta;
+    sl.holds_long = false;
     const uint64_t t = clock_ns();
-    for (size_t i = 0; i < k; ++i) {
-        take[i]->c.t_admit_ns = t;
-        s->pending.pop_front();
+    for (RequestPtr &r : take) {
+        r->c.t_admit_ns = t;
+        sl.holds_long = sl.holds_long || r->is_long;
     }
+    // Remove the admitted requests from the queue (they are in queue order).
+    size_t j = 0;
+    auto keep = std::remove_if(s->pending.begin(), s->pending.end(), [&](const RequestPtr &r) {
+        if (j < take.size() && r == take[j]) { ++j; return true; }
+        return false;
+    });
+    s->pending.erase(keep, s->pending.end());
     return take;
 }
 
@@ -424,10 +438,15 @@ void launcher_loop(recoil_server *s) {
         reap(s);
         std::unique_lock<std::mutex> lk(s->mu);
         bool busy = false;
+        uint32_t long_in_flight = 0;
         Slot *free_slot = nullptr;
         for (Slot &sl : s->slots) {
-            if (sl.busy) busy = true;
-            else if (!free_slot) free_slot = &sl;
+            if (sl.busy) {
+                busy = true;
+                long_in_flight += sl.holds_long;
+            } else if (!free_slot) {
+                free_slot = &sl;
+            }
         }
         if (s->stopping) {
             if (!busy) break;
@@ -436,7 +455,7 @@ void launcher_loop(recoil_server *s) {
             continue;
         }
         if (free_slot) {
-            std::vector<RequestPtr> take = admit_locked(s, *free_slot, !busy);
+            std::vector<RequestPtr> take = admit_locked(s, *free_slot, !busy, long_in_flight < s->cfg.long_streams);
             if (!take.empty()) {
                 free_slot->reqs = std::move(take);
                 free_slot->busy = true;
@@ -511,6 +530,8 @@ recoil_status recoil_server_create(const recoil_server_config *cfg, void *d_aren
     auto *s = new (std::nothrow) recoil_server();
     if (!s) return fail(RECOIL_ERR_INVALID_ARG, "server_create: out of memory");
     s->cfg = *cfg;
+    if (s->cfg.long_unit_bytes == 0) s->cfg.long_unit_bytes = 131072;
+    if (s->cfg.long_streams == 0) s->cfg.long_streams = std::max(1u, cfg->hip_streams / 2);
     s->arena = static_cast<unsigned char *>(d_arena);
     s->arena_bytes = arena_bytes;
     s->resident_end = resident_end;
@@ -586,6 +607,7 @@ recoil_status recoil_server_submit(recoil_server *s, uint32_t content, uint32_t 
         if (content >= s->contents.size()) return fail(RECOIL_ERR_INVALID_ARG, "server_submit: unknown content");
         r->content = s->contents[content];
         r->splits_asked = splits;
+        r->long_unit_bytes = s->cfg.long_unit_bytes;
         r->c.request_id = s->next_id++;
         r->c.tag = tag;
         r->c.content = content;

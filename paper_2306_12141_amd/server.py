@@ -24,10 +24,12 @@ class Server:
     """
 
     def __init__(self, arena, resident_bytes: int, hip_streams: int = 2, max_batch: int = 256,
-                 prep_threads: int = 4, items_per_launch: int = 1 << 17, tuning: Optional[Tuning] = None):
+                 prep_threads: int = 4, items_per_launch: int = 1 << 17, tuning: Optional[Tuning] = None,
+                 long_unit_bytes: int = 0, long_streams: int = 0):
         self.arena = arena
         cfg = ServerConfig(hip_streams, max_batch, prep_threads, items_per_launch, resident_bytes,
-                           tuning if tuning is not None else _lib.recoil_default_tuning())
+                           tuning if tuning is not None else _lib.recoil_default_tuning(), long_unit_bytes,
+                           long_streams, 0)
         self._h = C.c_void_p()
         check(_lib.recoil_server_create(C.byref(cfg), C.c_void_p(arena.data_ptr()), arena.numel(),
                                         C.byref(self._h)), "recoil_server_create")
