@@ -2,13 +2,14 @@
 """Recoil decode benchmark on one MI355X.
 
 Default workload: a single 256 MiB uint8 stream, iid Zipf(s = 1.1) over a
-seeded permutation of 256 symbols, n = 12, W = 32 interleaved lanes, encoded
-with 65536 splits. One step is one recoil_decode of the whole stream with the
-bitstream, table and metadata already resident in HBM. `value` is decoded
-output bytes per second (1 GB = 1e9 B) over the timed steps.
+seeded permutation of 256 symbols, n = 12, W = 64 interleaved lanes (--lanes),
+encoded with 65536 splits. One step is one recoil_decode of the whole stream
+with the bitstream, table and metadata already resident in HBM. `value` is
+decoded output bytes per second (1 GB = 1e9 B) over the timed steps.
 
-Also reported: the same stream at W = 64, the stream combined down to 16384 /
-4096 / 1024 / 256 splits (metadata and transferred bytes, GB/s), the dominant
+Also reported: the same stream at W = 32 (the workload measures both), the
+W = 32 stream combined down to 16384 / 4096 / 1024 / 256 splits (metadata and
+transferred bytes, GB/s), the host-to-device upload time, the dominant
 kernel's roofline position, and the CPU oracle timed on the host cores on a
 bounded sample of the same workload.
 
@@ -142,7 +143,11 @@ def run_c1(args, torch, np, rc, synth):
         w, k, b = (int(v) for v in args.shape.split(","))
         plan.set_tuning(waves=w, chunk_groups=k, blocks_per_cu=b)
     ws = plan.allocate_workspace()
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     plan.upload(ws)
+    torch.cuda.synchronize()
+    upload_s = time.perf_counter() - t_up
     out = plan.allocate_output()
     err = torch.zeros(1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -157,7 +162,8 @@ def run_c1(args, torch, np, rc, synth):
         "value": value, "ms_per_step": t["ms_per_step"], "exact": exact,
         "kernel_ms_mean": t["kernel_ms_mean"], "kernel_ms_median": t["kernel_ms_median"],
         "alg_bytes": alg_bytes, "achieved_gbs": achieved, "blob_info": info, "plan": plan,
-        "blob": blob, "symbols": s, "spec": spec,
+        "blob": blob, "symbols": s, "spec": spec, "upload_s": upload_s, "upload_bytes": plan.device_bytes,
+        "pcie_inclusive_gbs": out_bytes / (upload_s + t["kernel_ms_mean"] * 1e-3) / 1e9,
     }
     # Keep device memory for the caller to release.
     result["_buffers"] = (ws, out, err)
@@ -398,7 +404,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--lanes", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--lanes", type=int, default=64, choices=(32, 64),
+                    help="interleaved lanes of the headline encoding (the other is reported in extras)")
     ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU",
                     help="launch shape of the decode kernel (default 16,4,0)")
     ap.add_argument("--workload", default="c1", choices=("c1", "c3", "c4"))
@@ -409,7 +416,7 @@ def main():
     ap.add_argument("--c4-warmup", type=float, default=5.0, help="warm-up before the window (s)")
     ap.add_argument("--no-extras", action="store_true", help="skip the W=64 and combined-split runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="symbols in the oracle's sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28, help="symbols in the oracle's sample (default: all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES (for counter calibration)")
     args = ap.parse_args()
@@ -439,16 +446,24 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     base = run_c1(args, torch, np, rc, synth)
-    extras = {}
+    extras = {"upload": {"bytes": base["upload_bytes"], "ms": round(base["upload_s"] * 1e3, 3),
+                         "pcie_inclusive_decoded_gbs": round(base["pcie_inclusive_gbs"], 2)}}
     if not args.no_extras:
-        extras["combined"] = run_combined(args, base, torch, np, rc)
-        if args.lanes == 32:
-            other = argparse.Namespace(**{**vars(args), "lanes": 64})
-            r64 = run_c1(other, torch, np, rc, synth)
-            extras["w64"] = {"decoded_gbs": round(r64["value"], 2), "ms_per_step": round(r64["ms_per_step"], 4),
-                             "exact": r64["exact"], "metadata_bytes": r64["blob_info"].metadata_bytes,
-                             "roofline_frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4)}
-            del r64
+        # The same stream interleaved the other way (the workload names both), and
+        # the split-count sweep on the W = 32 encoding.
+        other_lanes = 32 if args.lanes == 64 else 64
+        other = run_c1(argparse.Namespace(**{**vars(args), "lanes": other_lanes}), torch, np, rc, synth)
+        extras[f"w{other_lanes}"] = {
+            "decoded_gbs": round(other["value"], 2), "ms_per_step": round(other["ms_per_step"], 4),
+            "exact": other["exact"], "metadata_bytes": other["blob_info"].metadata_bytes,
+            "roofline": {"bound": "hbm", "achieved": round(other["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(other["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(f"decode_units_c1_w{other_lanes}"),
+                         "alg_bytes_per_launch": other["alg_bytes"],
+                         "kernel_ms_mean": round(other["kernel_ms_mean"], 5)}}
+        w32 = other if other_lanes == 32 else base
+        extras["combined_w32"] = run_combined(args, w32, torch, np, rc)
+        del other, w32
     cpu = None
     if not args.no_cpu:
         cpu = cpu_oracle_baseline(base["spec"], args.cpu_sample, np)

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librecoil.so")
 BUILD = os.path.join(HERE, "_build")
 
-HOST_SOURCES = ["host/codec.cpp", "host/plan.cpp", "host/batch.cpp", "host/server.cpp"]
+HOST_SOURCES = ["host/codec.cpp", "host/plan.cpp", "host/batch.cpp", "host/server.cpp", "host/staging.cpp"]
 DEVICE_SOURCES = ["device/decode.hip", "device/batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

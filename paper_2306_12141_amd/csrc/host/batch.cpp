@@ -193,12 +193,12 @@ recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t 
         const PlanData &pl = b.plans[i];
         const StreamDesc &d = b.descs[i];
         if (pl.blob->n_words())
-            e = hipMemcpyAsync(base + d.words_off, pl.blob->words(), 2 * pl.blob->n_words(), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(base + d.lut_off, pl.lut.data(), pl.lut.size(), hipMemcpyHostToDevice, stream);
+            e = stage_h2d(base + d.words_off, pl.blob->words(), 2 * pl.blob->n_words(), stream);
+        if (e == hipSuccess) e = stage_h2d(base + d.lut_off, pl.lut.data(), pl.lut.size(), stream);
         if (e == hipSuccess && !pl.meta.empty())
-            e = hipMemcpyAsync(base + d.meta_off, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), hipMemcpyHostToDevice, stream);
+            e = stage_h2d(base + d.meta_off, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), stream);
         if (e == hipSuccess && !pl.lanes.empty())
-            e = hipMemcpyAsync(base + d.lanes_off, pl.lanes.data(), pl.lanes.size() * 4, hipMemcpyHostToDevice, stream);
+            e = stage_h2d(base + d.lanes_off, pl.lanes.data(), pl.lanes.size() * 4, stream);
     }
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("batch_upload: ") + hipGetErrorString(e));
     return upload_items(b, d_ws, stream);

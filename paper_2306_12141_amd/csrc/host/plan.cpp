@@ -207,10 +207,10 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t byt
     char *base = static_cast<char *>(d_ws);
     const BlobData &b = *pl.blob;
     hipError_t e = hipSuccess;
-    if (b.n_words()) e = hipMemcpyAsync(base + pl.off_words, b.words(), 2 * b.n_words(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lut, pl.lut.data(), pl.lut.size(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, hipMemcpyHostToDevice, stream);
+    if (b.n_words()) e = stage_h2d(base + pl.off_words, b.words(), 2 * b.n_words(), stream);
+    if (e == hipSuccess) e = stage_h2d(base + pl.off_lut, pl.lut.data(), pl.lut.size(), stream);
+    if (e == hipSuccess) e = stage_h2d(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), stream);
+    if (e == hipSuccess) e = stage_h2d(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, stream);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_upload: ") + hipGetErrorString(e));
     return RECOIL_OK;
 }

@@ -36,6 +36,12 @@ void build_table(const BlobData &blob, PlanData &plan);
 recoil_status build_units_combined(const std::shared_ptr<const BlobData> &blob, uint32_t target, PlanData &plan,
                                    uint64_t *packed_bytes);
 
+// Host-to-device copy of pageable host memory: through two pinned staging
+// buffers of the calling thread, so it runs at DMA speed. The copies are queued
+// on `stream` in order; the call returns once the last one is queued (a staging
+// buffer is reused only after its previous copy has completed).
+hipError_t stage_h2d(void *dst, const void *src, size_t bytes, hipStream_t stream);
+
 // Bytes of the words section for B words (padded so chunks can be fetched whole).
 inline size_t words_section_bytes(uint64_t n_words) { return ws_align(2 * (n_words + kChunkPadWords)); }
 

@@ -587,8 +587,9 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
         s->resident_used += wbytes + ws_align(ct.lut_bytes);
     }
     hipError_t e = hipSuccess;
-    if (bp->n_words()) e = hipMemcpy(s->arena + ct.words_off, bp->words(), 2 * bp->n_words(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->arena + ct.lut_off, probe.lut.data(), probe.lut.size(), hipMemcpyHostToDevice);
+    if (bp->n_words()) e = stage_h2d(s->arena + ct.words_off, bp->words(), 2 * bp->n_words(), nullptr);
+    if (e == hipSuccess) e = stage_h2d(s->arena + ct.lut_off, probe.lut.data(), probe.lut.size(), nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("server_add_content: ") + hipGetErrorString(e));
     std::lock_guard<std::mutex> lk(s->mu);
     *content_id = (uint32_t)s->contents.size();
