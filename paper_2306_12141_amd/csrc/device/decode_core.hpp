@@ -166,6 +166,7 @@ struct PairDecoder {
     int32_t fq[S];         // lowest chunk held in the ring (the next fetch is fq - 1)
     uint32_t po[S];        // byte offset from the top third of the third that chunk fq - 1 goes to
     uint32_t presync;      // leading groups of the pair that need the predicated body
+    bool sync_lean;        // no unit of the pair is the stream's last (ragged top group, 32-bit states)
     // Per lane.
     uint32_t x, rec, act;
     uint32_t my_top, my_ghi, my_steps, lane_off;
@@ -221,6 +222,7 @@ struct PairDecoder {
     __device__ bool begin(uint32_t pair) {
         const uint32_t u0 = pair * S;
         bool any = false;
+        bool has_last = false;
         uint32_t sync_max = 0;
         int32_t cur[S];
         uint32_t top[S], ghi[S];
@@ -238,10 +240,12 @@ struct PairDecoder {
             steps[h] = (valid && top[h] + 1 > glo) ? top[h] + 1 - glo : 0u;
             uint32_t sync = valid ? top[h] - ghi[h] + 1 : 0u;
             if (last) sync = (p.n_symbols % W) ? 1u : 0u;
+            has_last = has_last || last;
             sync_max = max(sync_max, sync);
             any = any || steps[h] > 0;
         }
         presync = sync_max;
+        sync_lean = !has_last;
         top0 = top[0];
         top_min = S == 2 ? min(top[0], top[S - 1]) : top[0];
         my_top = S == 2 && upper ? top[S - 1] : top[0];
@@ -327,10 +331,28 @@ struct PairDecoder {
         }
     }
 
-    template <bool PRED, uint32_t... G_IDX>
+    // Synchronisation group of a pair whose units are all within their own
+    // groups and below the stream's last group: only the switching-on of lanes
+    // and the stores of groups above a unit's completion point are predicated.
+    // Lanes not yet on decode garbage that is dropped when they switch on.
+    template <uint32_t G_IDX>
+    __device__ inline void group_sync(uint32_t k, uint32_t &a, uint32_t &e) {
+        if (k == act) x = rec & 0xFFFFu;
+        read_step<G_IDX>(k >= act && x < kL, a, e);
+        const uint32_t s = T::step(lut, x, n, mask);
+        const uint32_t h = my_top - k;
+        if (h <= my_ghi) static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
+    }
+
+    // Bodies of a super-step: unpredicated, synchronisation, fully predicated.
+    static constexpr int kFast = 0, kSync = 1, kPred = 2;
+
+    template <int MODE, uint32_t... G_IDX>
     __device__ inline void groups(std::integer_sequence<uint32_t, G_IDX...>, uint32_t k, uint32_t &a, uint32_t &e) {
-        if constexpr (PRED) {
+        if constexpr (MODE == kPred) {
             (group_pred<G_IDX>(k + G_IDX, a, e), ...);
+        } else if constexpr (MODE == kSync) {
+            (group_sync<G_IDX>(k + G_IDX, a, e), ...);
         } else {
             unsigned char *outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top0 - k) * W * sizeof(Sym);
             (group_fast<G_IDX>(a, e, outh), ...);
@@ -343,12 +365,12 @@ struct PairDecoder {
     // most C words, so a unit keeps at least C words resident, and reads stay
     // within the ring plus its mirror.) Returns false if a unit read past its
     // first word (corrupt split data).
-    template <bool PRED, uint32_t KK = K>
+    template <int MODE, uint32_t KK = K>
     __device__ inline bool super_step(uint32_t k) {
         uint32_t ld = 0;
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
-            if ((!PRED || steps[h] > k) && fq[h] > 0 && res[h] < 2 * (int32_t)C) ld |= 1u << h;
+            if ((MODE != kPred || steps[h] > k) && fq[h] > 0 && res[h] < 2 * (int32_t)C) ld |= 1u << h;
         uint32_t a = ua[0], e = S == 2 ? ua[S - 1] : 0u;
         if (ld) {
             // One load for the whole wave, each unit's lanes addressing their own
@@ -363,13 +385,13 @@ struct PairDecoder {
             }
             Chunk pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) +
                                                          (off + col * (uint32_t)sizeof(Chunk)));
-            groups<PRED>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
+            groups<MODE>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
             asm volatile("" : "+v"(pre));
 #pragma unroll
             for (uint32_t h = 0; h < S; ++h)
                 if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(po[h], pre);
         } else {
-            groups<PRED>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
+            groups<MODE>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
         }
         bool ok = true;
         uint32_t a_end = a;
@@ -402,7 +424,16 @@ struct PairDecoder {
         // of the pair does.
         bool ok = true;
         uint32_t k = 0;
-        for (; ok && k < kmax && k < presync; k += K / 2) ok = super_step<true, K / 2>(k);
+        // The lean body needs every unit within its own groups for the whole
+        // lead-in; it does not track which lanes are on, so afterwards (when all
+        // are) the flag is set for the predicated body of the end.
+        const uint32_t lead = (presync + K / 2 - 1) / (K / 2) * (K / 2);
+        if (sync_lean && lead <= kmin) {
+            for (; ok && k < presync; k += K / 2) ok = super_step<kSync, K / 2>(k);
+            active = true;
+        } else {
+            for (; ok && k < kmax && k < presync; k += K / 2) ok = super_step<kPred, K / 2>(k);
+        }
         // From here every state of every unit is exact, so a unit that has
         // decoded its own groups may run on into the groups below: it stores
         // there the symbols the unit below stores too, and reads that unit's
@@ -417,10 +448,10 @@ struct PairDecoder {
         for (uint32_t h = 0; h < S; ++h)
             run_on = run_on && res[h] + fq[h] * (int32_t)C >= (int32_t)((kend - k) * W);
         if (run_on) {
-            for (; ok && k < kmax; k += K) ok = super_step<false>(k);
+            for (; ok && k < kmax; k += K) ok = super_step<kFast>(k);
         } else {
-            for (; ok && k + K <= kmin; k += K) ok = super_step<false>(k);
-            for (; ok && k < kmax; k += K) ok = super_step<true>(k);
+            for (; ok && k + K <= kmin; k += K) ok = super_step<kFast>(k);
+            for (; ok && k < kmax; k += K) ok = super_step<kPred>(k);
         }
         if (!ok && lane == 0) atomicOr(p.err, kDevErrUnderflow);
     }
