@@ -127,6 +127,14 @@ def cpu_oracle_baseline(spec, sample_symbols: int, np):
                       f"all {splits} decode units over {cores} std::threads; {dt:.2f} s wall"}
 
 
+def algorithmic_bytes(spec, info, runs):
+    """Bytes a decode must move: the symbols written, the bitstream read, per run
+    the top unit's record (16 B), the bottom unit's last group (4 B) and the top
+    unit's lane records (4 W B), and the decode table (2^n x 4 B)."""
+    return (spec.n_symbols * spec.symbol_bytes + 2 * info.n_words + runs * (20 + 4 * info.lanes)
+            + (4 << spec.quant_bits))
+
+
 def run_c1(args, torch, np, rc, synth):
     lanes = args.lanes
     spec = synth.c1_spec(lanes)
@@ -140,8 +148,9 @@ def run_c1(args, torch, np, rc, synth):
         f"in {time.perf_counter() - t0:.1f}s")
     plan = rc.Plan(blob)
     if args.shape:
-        w, k, b = (int(v) for v in args.shape.split(","))
-        plan.set_tuning(waves=w, chunk_groups=k, blocks_per_cu=b)
+        v = [int(x) for x in args.shape.split(",")]
+        plan.set_tuning(waves=v[0], chunk_groups=v[1], blocks_per_cu=v[2], units_per_run=v[3] if len(v) > 3 else 0)
+    shape = plan.shape()
     ws = plan.allocate_workspace()
     # First upload (includes one-time driver and staging set-up), then a warm one.
     upload = []
@@ -158,7 +167,7 @@ def run_c1(args, torch, np, rc, synth):
     t = time_decode(plan, ws, out, err, args.steps, args.warmup, torch)
     exact = check_exact(plan, out, s, err, np)
     out_bytes = spec.n_symbols * spec.symbol_bytes
-    alg_bytes = out_bytes + 2 * info.n_words + plan.metadata_device_bytes + (4 << spec.quant_bits)
+    alg_bytes = algorithmic_bytes(spec, info, shape.runs)
     value = out_bytes / (t["ms_per_step"] * 1e-3) / 1e9
     achieved = alg_bytes / (t["kernel_ms_mean"] * 1e-3) / 1e9
     log(f"W={lanes}: {t['ms_per_step']:.4f} ms/step, {value:.1f} GB/s decoded, exact={exact}")
@@ -169,7 +178,24 @@ def run_c1(args, torch, np, rc, synth):
         "blob": blob, "symbols": s, "spec": spec, "upload_s": upload_s, "upload_cold_s": upload[0],
         "upload_bytes": plan.device_bytes,
         "pcie_inclusive_gbs": out_bytes / (upload_s + t["kernel_ms_mean"] * 1e-3) / 1e9,
+        "shape": {"blocks": shape.blocks, "waves_per_block": shape.waves_per_block,
+                  "units_per_run": shape.units_per_run, "runs": shape.runs},
     }
+    if not args.no_extras and shape.units_per_run != 1:
+        # The same decode using every split point (one run per unit).
+        kg = int(args.shape.split(",")[1]) if args.shape else 8
+        plan.set_tuning(waves=shape.waves_per_block, chunk_groups=kg, units_per_run=1)
+        one = plan.shape()
+        t1 = time_decode(plan, ws, out, err, args.steps, args.warmup, torch)
+        ok1 = check_exact(plan, out, s, err, np)
+        result["every_split_point"] = {
+            "decoded_gbs": round(out_bytes / (t1["ms_per_step"] * 1e-3) / 1e9, 2),
+            "ms_per_step": round(t1["ms_per_step"], 5), "kernel_ms_mean": round(t1["kernel_ms_mean"], 5),
+            "exact": ok1, "runs": one.runs,
+            "roofline_frac": round(algorithmic_bytes(spec, info, one.runs) / (t1["kernel_ms_mean"] * 1e-3) / 1e9
+                                   / HBM_PEAK_GBS, 4)}
+        log(f"W={lanes} every split point: {t1['ms_per_step']:.4f} ms/step, exact={ok1}")
+        plan.set_tuning(waves=shape.waves_per_block, chunk_groups=kg, units_per_run=shape.units_per_run)
     # Keep device memory for the caller to release.
     result["_buffers"] = (ws, out, err)
     return result
@@ -208,7 +234,7 @@ def run_combined(args, base, torch, np, rc):
         t = time_decode(plan, ws, out, err, max(3, args.steps // 2), 2, torch)
         exact = check_exact(plan, out, s, err, np)
         gbs = len(s) / (t["ms_per_step"] * 1e-3) / 1e9
-        rows.append({"splits": info.splits, "metadata_bytes": info.metadata_bytes,
+        rows.append({"splits": info.splits, "runs": plan.shape().runs, "metadata_bytes": info.metadata_bytes,
                      "transferred_bytes": info.total_bytes, "decoded_gbs": round(gbs, 2),
                      "ms": round(t["ms_per_step"], 4), "exact": exact})
         log(f"combined to {info.splits}: meta {info.metadata_bytes} B, {gbs:.1f} GB/s, exact={exact}")
@@ -429,8 +455,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--lanes", type=int, default=64, choices=(32, 64),
                     help="interleaved lanes of the headline encoding (the other is reported in extras)")
-    ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU",
-                    help="launch shape of the decode kernel (default 16,4,0)")
+    ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU[,UNITS_PER_RUN]",
+                    help="launch shape of the decode kernel (default 16,8,0,0: units per run chosen at launch)")
     ap.add_argument("--workload", default="c1", choices=("c1", "c3", "c4"))
     ap.add_argument("--c3-streams", type=int, default=4096, help="streams in the batched workload")
     ap.add_argument("--c4-corpus", type=int, default=128, help="resident streams in the serving corpus")
@@ -472,6 +498,8 @@ def main():
     extras = {"upload": {"bytes": base["upload_bytes"], "ms": round(base["upload_s"] * 1e3, 3),
                          "first_ms": round(base["upload_cold_s"] * 1e3, 3),
                          "pcie_inclusive_decoded_gbs": round(base["pcie_inclusive_gbs"], 2)}}
+    if "every_split_point" in base:
+        extras["every_split_point"] = base["every_split_point"]
     if not args.no_extras:
         # The same stream interleaved the other way (the workload names both), and
         # the split-count sweep on the W = 32 encoding.
@@ -480,6 +508,7 @@ def main():
         extras[f"w{other_lanes}"] = {
             "decoded_gbs": round(other["value"], 2), "ms_per_step": round(other["ms_per_step"], 4),
             "exact": other["exact"], "metadata_bytes": other["blob_info"].metadata_bytes,
+            "launch": other["shape"],
             "roofline": {"bound": "hbm", "achieved": round(other["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(other["achieved_gbs"] / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(f"decode_units_c1_w{other_lanes}"),
@@ -516,7 +545,7 @@ def main():
             "n_symbols": info.n_symbols, "n_words": info.n_words, "splits": info.splits,
             "lanes": args.lanes, "quant_bits": info.quant_bits,
             "metadata_bytes": info.metadata_bytes, "container_bytes": info.total_bytes,
-            "bit_exact": base["exact"],
+            "bit_exact": base["exact"], "launch": base["shape"],
         },
         "roofline": {
             "bound": "hbm",

@@ -103,10 +103,20 @@ typedef struct {
  *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
  *                  ring holds 4 K W words (3 K W ring + K W mirror)
  *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)
- *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit) */
+ *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit)
+ *   units_per_run  single-stream decode only: k consecutive decode units are decoded
+ *                  as one, from the highest unit's split point down to the lowest unit's
+ *                  last group (the decoder uses every k-th split point, as combining
+ *                  the splits would, Sec. 3.3, without re-packing). 1: every split
+ *                  point; 0: chosen at launch, about two runs per resident unit slot. */
 typedef struct {
-    uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu;
+    uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu, units_per_run;
 } recoil_tuning;
+
+/* Grid of a single-stream decode and the runs it decodes (recoil_plan_shape). */
+typedef struct {
+    uint32_t blocks, waves_per_block, units_per_run, runs;
+} recoil_decode_shape;
 
 typedef struct recoil_blob recoil_blob;   /* immutable encoded stream; safe to share between threads */
 typedef struct recoil_plan recoil_plan;   /* host-side decode plan for one blob on the GPU */
@@ -182,9 +192,14 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, siz
 /* Size in bytes of the split metadata as uploaded (part of device_bytes). */
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
 /* Launch shape used by recoil_decode for this plan (default: 16 waves per
- * workgroup; K = 8 groups per super-step for uint8 tables, 4 for uint16).
+ * workgroup; K = 8 groups per super-step for uint8 tables, 4 for uint16;
+ * units_per_run 0). pairs_per_wave is ignored.
  * Errors: INVALID_ARG (unsupported shape). */
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *tuning);
+/* The grid and runs recoil_decode would use on the current device (all zero
+ * when no decode kernel runs: empty or single-symbol streams). Launches nothing.
+ * Errors: INVALID_ARG, HIP (occupancy query failed). */
+recoil_status recoil_plan_shape(const recoil_plan *plan, recoil_decode_shape *out);
 void recoil_plan_free(recoil_plan *plan);
 
 /*

@@ -137,9 +137,16 @@ class Plan:
     def metadata_device_bytes(self) -> int:
         return _lib.recoil_plan_metadata_device_bytes(self._h)
 
-    def set_tuning(self, waves: int = 16, chunk_groups: int = 4, blocks_per_cu: int = 0) -> None:
-        t = _lib.Tuning(waves, chunk_groups, 1, blocks_per_cu)
+    def set_tuning(self, waves: int = 16, chunk_groups: int = 4, blocks_per_cu: int = 0,
+                   units_per_run: int = 0) -> None:
+        t = _lib.Tuning(waves, chunk_groups, 1, blocks_per_cu, units_per_run)
         check(_lib.recoil_plan_set_tuning(self._h, C.byref(t)), "recoil_plan_set_tuning")
+
+    def shape(self) -> _lib.DecodeShape:
+        """Grid and runs recoil_decode uses for this plan on the current device."""
+        sh = _lib.DecodeShape()
+        check(_lib.recoil_plan_shape(self._h, C.byref(sh)), "recoil_plan_shape")
+        return sh
 
     def allocate_workspace(self, device="cuda"):
         import torch

@@ -74,10 +74,16 @@ def check(status: int, what: str) -> None:
 
 
 class Tuning(C.Structure):
-    _fields_ = [("waves", u32), ("chunk_groups", u32), ("pairs_per_wave", u32), ("blocks_per_cu", u32)]
+    _fields_ = [("waves", u32), ("chunk_groups", u32), ("pairs_per_wave", u32), ("blocks_per_cu", u32),
+                ("units_per_run", u32)]
+
+
+class DecodeShape(C.Structure):
+    _fields_ = [("blocks", u32), ("waves_per_block", u32), ("units_per_run", u32), ("runs", u32)]
 
 
 recoil_plan_set_tuning = _sig("recoil_plan_set_tuning", [P, C.POINTER(Tuning)])
+recoil_plan_shape = _sig("recoil_plan_shape", [P, C.POINTER(DecodeShape)])
 recoil_default_tuning = _sig("recoil_default_tuning", [], Tuning)
 recoil_batch_create = _sig("recoil_batch_create", [P, u32, C.POINTER(Tuning), C.POINTER(P), C.POINTER(sz),
                                                    C.POINTER(sz)])

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
     __syncthreads();
     const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t npairs = (p.units + D::S - 1) / D::S;
+    const uint32_t npairs = (p.runs + D::S - 1) / D::S;
     const uint32_t first = blockIdx.x * WAVES + wave, stride = gridDim.x * WAVES;
     D d(p, base + L::TABLE, base + L::PAD + wave * L::WAVE_LDS, lane);
     // Pairs are dealt out by position. The issue arbiter favours older waves,
@@ -102,33 +102,44 @@ int units_occupancy(uint32_t quant_bits) {
 }
 
 template <int W, typename Sym, int K, int WAVES>
-hipError_t launch_units(const DecodeParams &p, uint32_t blocks_per_cu, hipStream_t stream) {
+hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     int per_cu = units_occupancy<W, Sym, K, WAVES>(p.quant_bits);
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    if (blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)blocks_per_cu);
-    const uint32_t pairs = (p.units + 64 / W - 1) / (64 / W);
+    if (t.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)t.blocks_per_cu);
+    const uint32_t resident = (uint32_t)(device_cus() * per_cu);
+    DecodeParams q = p;
+    q.run = t.units_per_run ? t.units_per_run : auto_units_per_run(p.units, (uint64_t)resident * WAVES * (64 / W));
+    q.run = std::min(q.run, std::max(p.units, 1u));
+    q.runs = (uint32_t)(((uint64_t)p.units + q.run - 1) / q.run);
+    const uint32_t pairs = (q.runs + 64 / W - 1) / (64 / W);
     const uint32_t need = (pairs + WAVES - 1) / WAVES;
-    const uint32_t blocks = std::max<uint32_t>(1u, std::min<uint32_t>(need, (uint32_t)(device_cus() * per_cu)));
+    const uint32_t blocks = std::max<uint32_t>(1u, std::min<uint32_t>(need, resident));
+    if (shape) {
+        *shape = DecodeShape{blocks, (uint32_t)WAVES, q.run, q.runs};
+        return hipSuccess;
+    }
     const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits);
-    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, p);
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
     return hipGetLastError();
 }
 
 template <int W, typename Sym>
-hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream) {
-    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t.blocks_per_cu, stream);
-    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t.blocks_per_cu, stream);
-    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t.blocks_per_cu, stream);
-    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16>(p, t.blocks_per_cu, stream);
+hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
+    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16>(p, t, stream, shape);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
-                         hipStream_t stream) {
+                         hipStream_t stream, DecodeShape *shape) {
+    if (shape) *shape = DecodeShape{0, 0, 0, 0};
     if (p.n_symbols == 0) return hipSuccess;
     if (p.single_symbol) {
+        if (shape) return hipSuccess;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((p.n_symbols + 255) / 256, 65536);
         if (symbol_bytes == 1)
             hipLaunchKernelGGL(fill_symbol<uint8_t>, dim3(blocks), dim3(256), 0, stream,
@@ -138,10 +149,10 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
     }
-    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t>(p, t, stream);
-    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t>(p, t, stream);
-    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t>(p, t, stream);
-    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t>(p, t, stream);
+    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t>(p, t, stream, shape);
+    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t>(p, t, stream, shape);
     return hipErrorInvalidValue;
 }
 

@@ -37,20 +37,36 @@ struct DecodeParams {
     uint32_t *err;              // device error word
     uint64_t n_symbols;
     uint32_t units;
+    uint32_t run;               // consecutive units decoded as one (Sec. 3.3): 1 uses every split point
+    uint32_t runs;              // ceil(units / run); run r covers units [r run, min((r + 1) run, units))
     uint32_t quant_bits;
     uint32_t fill_symbol;       // used when the table holds a single symbol (f = 2^n)
     uint32_t single_symbol;     // nonzero: the stream is one repeated symbol
 };
 
 // Launch shape of the single-stream kernel: waves per workgroup (8 or 16),
-// groups per super-step K (4 or 8), workgroups per CU
-// cap (0 = occupancy limit).
+// groups per super-step K (4 or 8), workgroups per CU cap (0 = occupancy
+// limit), units per run (0 = chosen from the number of resident waves).
 struct DecodeTuning {
-    uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0;
+    uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0, units_per_run = 0;
 };
 
-// Launcher (decode.hip). Returns hipSuccess or the launch error.
+// Units per run when the tuning leaves it open: about two runs for every unit
+// slot of the resident grid (slots = resident waves x units per wave).
+inline uint32_t auto_units_per_run(uint32_t units, uint64_t slots) {
+    const uint64_t k = slots ? units / (2 * slots) : 1;
+    return k < 1 ? 1u : (uint32_t)k;
+}
+
+// Grid of a single-stream launch and the runs it decodes.
+struct DecodeShape {
+    uint32_t blocks, waves, units_per_run, runs;
+};
+
+// Launcher (decode.hip). Returns hipSuccess or the launch error. With shape
+// non-null nothing is launched: the grid and runs a launch would use are
+// stored there (all zero when no decode kernel would run).
 hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
-                         hipStream_t stream);
+                         hipStream_t stream, DecodeShape *shape = nullptr);
 
 }  // namespace recoil

@@ -219,8 +219,12 @@ struct PairDecoder {
     // Lane slice address for chunks in the top third of the ring.
     __device__ inline uint32_t lane_ring_addr() const { return ring_addr(upper, 2 * (int32_t)C + (int32_t)(K * col + K - 1)); }
 
+    // A run of consecutive units decodes as one unit: it starts from its
+    // highest unit's split point (records, first word, first group, completion
+    // point) and ends at its lowest unit's last group; the split points in
+    // between are not used (Sec. 3.3).
     __device__ bool begin(uint32_t pair) {
-        const uint32_t u0 = pair * S;
+        const uint32_t r0 = pair * S;
         bool any = false;
         bool has_last = false;
         uint32_t sync_max = 0;
@@ -228,11 +232,16 @@ struct PairDecoder {
         uint32_t top[S], ghi[S];
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
-            const uint32_t u = u0 + h;
-            const bool valid = u < p.units;
-            const bool last = valid && u + 1 == p.units;
+            const uint32_t r = r0 + h;
+            const bool valid = r < p.runs;
+            const uint32_t lo = r * p.run;
+            const uint32_t hi = valid ? min(lo + p.run, p.units) - 1u : 0u;
+            const bool last = valid && hi + 1 == p.units;
             UnitMeta m = {0, 0, 0, 1};
-            if (valid) m = p.meta[u];
+            if (valid) {
+                m = p.meta[hi];
+                m.glo = p.meta[lo].glo;
+            }
             cur[h] = (int32_t)uni(m.next);
             top[h] = uni(m.top);
             ghi[h] = uni(m.ghi);
@@ -253,10 +262,11 @@ struct PairDecoder {
         my_steps = S == 2 && upper ? steps[S - 1] : steps[0];
         // Fast-body store offset of this lane from unit 0's group pointer.
         lane_off = (coder + (S == 2 ? upper * W * (my_top - top0) : 0u)) * (uint32_t)sizeof(Sym);
-        const uint32_t mine = u0 + upper;
-        const bool my_valid = mine < p.units;
-        const bool my_last = my_valid && mine + 1 == p.units;
-        rec = my_valid ? p.lanes[(uint64_t)mine * W + coder] : 0u;
+        const uint32_t mine = r0 + upper;
+        const bool my_valid = mine < p.runs;
+        const uint32_t my_hi = my_valid ? min(mine * p.run + p.run, p.units) - 1u : 0u;
+        const bool my_last = my_valid && my_hi + 1 == p.units;
+        rec = my_valid ? p.lanes[(uint64_t)my_hi * W + coder] : 0u;
         x = my_last ? rec : 0u;
         active = my_last;
         act = my_last ? 0u : (rec >> 16);

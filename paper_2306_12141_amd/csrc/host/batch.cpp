@@ -95,7 +95,7 @@ struct recoil_graph {
 
 extern "C" {
 
-recoil_tuning recoil_default_tuning(void) { return recoil_tuning{16, 4, 2, 0}; }
+recoil_tuning recoil_default_tuning(void) { return recoil_tuning{16, 4, 2, 0, 0}; }
 
 recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t count, const recoil_tuning *tuning,
                                   recoil_batch **out, size_t *workspace_bytes, size_t *output_bytes) {
@@ -249,6 +249,8 @@ recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const vo
         p.err = d_error;
         p.n_symbols = d.n_symbols;
         p.units = d.units;
+        p.run = 1;
+        p.runs = d.units;
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
         p.single_symbol = d.single_symbol;

@@ -225,17 +225,14 @@ recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *t) 
     plan->d.tuning.waves = t->waves;
     plan->d.tuning.chunk_groups = t->chunk_groups;
     plan->d.tuning.blocks_per_cu = t->blocks_per_cu;
+    plan->d.tuning.units_per_run = t->units_per_run;
     return RECOIL_OK;
 }
 
-recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_out, uint32_t *d_error,
-                            hipStream_t stream) {
+namespace {
+
+recoil::DecodeParams decode_params(const recoil::PlanData &pl, const void *d_ws, void *d_out, uint32_t *d_error) {
     using namespace recoil;
-    if (!plan || !d_ws || !d_error || (!d_out && plan->d.blob->n_symbols))
-        return fail(RECOIL_ERR_INVALID_ARG, "decode: bad arguments");
-    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
-        return fail(RECOIL_ERR_ALIGNMENT, "decode: output must be 16-byte and workspace 256-byte aligned");
-    const PlanData &pl = plan->d;
     const BlobData &b = *pl.blob;
     const char *base = static_cast<const char *>(d_ws);
     DecodeParams p{};
@@ -247,11 +244,39 @@ recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_o
     p.err = d_error;
     p.n_symbols = b.n_symbols;
     p.units = b.splits();
+    p.run = 1;
+    p.runs = p.units;
     p.quant_bits = b.quant_bits;
     p.fill_symbol = pl.fill_symbol;
     p.single_symbol = pl.single_symbol ? 1u : 0u;
-    hipError_t e = launch_decode(p, b.lanes, b.symbol_bytes, pl.tuning, stream);
+    return p;
+}
+
+}  // namespace
+
+recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_out, uint32_t *d_error,
+                            hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws || !d_error || (!d_out && plan->d.blob->n_symbols))
+        return fail(RECOIL_ERR_INVALID_ARG, "decode: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(RECOIL_ERR_ALIGNMENT, "decode: output must be 16-byte and workspace 256-byte aligned");
+    const PlanData &pl = plan->d;
+    const DecodeParams p = decode_params(pl, d_ws, d_out, d_error);
+    hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+recoil_status recoil_plan_shape(const recoil_plan *plan, recoil_decode_shape *out) {
+    using namespace recoil;
+    if (!plan || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_shape: bad arguments");
+    const PlanData &pl = plan->d;
+    DecodeShape sh{};
+    hipError_t e = launch_decode(decode_params(pl, nullptr, nullptr, nullptr), pl.blob->lanes, pl.blob->symbol_bytes,
+                                 pl.tuning, nullptr, &sh);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_shape: ") + hipGetErrorString(e));
+    *out = recoil_decode_shape{sh.blocks, sh.waves, sh.units_per_run, sh.runs};
     return RECOIL_OK;
 }
 

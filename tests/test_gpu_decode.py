@@ -34,9 +34,11 @@ def rc():
     return m
 
 
-def gpu_decode(rc, blob, poison=(0xA5, 0x5A)):
+def gpu_decode(rc, blob, poison=(0xA5, 0x5A), **tuning):
     """Decode twice, into buffers pre-filled with two patterns; both must agree."""
     plan = rc.Plan(blob)
+    if tuning:
+        plan.set_tuning(**tuning)
     ws = plan.allocate_workspace()
     plan.upload(ws)
     outs = []
@@ -102,6 +104,95 @@ def test_streams(rc, ci):
     s = _syms(1000 + ci, N, A, dt, z)
     blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
     assert np.array_equal(gpu_decode(rc, blob), s)
+
+
+RUN_CASES = [
+    # (lanes, n, symbol dtype, alphabet, N, splits, zipf exponent or None)
+    (32, 11, np.uint8, 256, 200_003, 29, 1.1),
+    (64, 12, np.uint8, 256, 300_001, 23, 1.3),
+    (32, 12, np.uint16, 4096, 120_003, 11, 1.0),
+    (64, 12, np.uint16, 4096, 90_001, 7, None),
+]
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 10_000])
+@pytest.mark.parametrize("ci", range(len(RUN_CASES)), ids=[f"W{c[0]}_{np.dtype(c[2]).name}_M{c[5]}" for c in RUN_CASES])
+def test_units_per_run(rc, ci, k):
+    """Runs of k consecutive units decoded as one (the last run ragged; k >= M is
+    the whole stream as one unit, i.e. the serial interleaved decoder)."""
+    W, n, dt, A, N, M, z = RUN_CASES[ci]
+    _say("case runs", RUN_CASES[ci], k)
+    s = _syms(2000 + ci, N, A, dt, z)
+    blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
+    assert np.array_equal(gpu_decode(rc, blob, chunk_groups=8 if dt == np.uint8 else 4, units_per_run=k), s)
+
+
+def test_units_per_run_shape(rc):
+    """The shape query reports the runs a launch decodes; 0 chooses about two runs per unit slot."""
+    s = _syms(77, 1 << 20, 256, np.uint8, 1.1)
+    blob = rc.encode(s, lanes=64, quant_bits=12, splits=4096)
+    M = blob.splits
+    assert M > 1000
+    plan = rc.Plan(blob)
+    plan.set_tuning(waves=16, chunk_groups=8, units_per_run=3)
+    sh = plan.shape()
+    assert sh.units_per_run == 3 and sh.runs == -(-M // 3) and sh.waves_per_block == 16
+    plan.set_tuning(waves=16, chunk_groups=8, units_per_run=0)
+    sh = plan.shape()
+    assert sh.units_per_run >= 1 and sh.runs == -(-M // sh.units_per_run)
+    assert sh.blocks * sh.waves_per_block * 2 >= sh.runs or sh.units_per_run == 1
+
+
+def test_random_split_sets_runs(rc, orc):
+    """Irregular oracle-built split sets decoded in runs of 2 and 3 units."""
+    from tests import _fmt
+    W, N = 64, 30_000
+    s = _syms(98, N, 256, np.uint8, 1.2)
+    p = orc.params(lanes=W, quant_bits=12)
+    f = orc.quantize(np.bincount(s, minlength=256).astype(np.uint64), 12)
+    enc = orc.encode(s, p, 1, freq=f)
+    hdr = _fmt.parse(enc.container())
+    rng = np.random.default_rng(6)
+    cands = []
+    for k in rng.choice(hdr["B"], size=300, replace=False):
+        c = enc.candidate_at(int(k))
+        if c is not None:
+            cands.append(c)
+    cands.sort(key=lambda c: c.pos)
+    for trial in range(4):
+        pick = sorted(rng.choice(len(cands), size=min(len(cands), 4 + 7 * trial), replace=False))
+        chosen = [cands[i] for i in pick]
+        chosen = [c for i, c in enumerate(chosen) if all(c.imin >= d.imin for d in chosen[:i])]
+        cont = orc.assemble(p, N, f, hdr["words"], hdr["final"], [c.pos for c in chosen],
+                            np.stack([c.states for c in chosen]), np.stack([c.indices for c in chosen]))
+        for k in (2, 3):
+            assert np.array_equal(gpu_decode(rc, rc.Blob.from_bytes(cont), chunk_groups=8, units_per_run=k), s)
+
+
+@pytest.mark.parametrize("W", [32, 64])
+def test_c1_full_size(rc, W):
+    """The 256 MiB Zipf(1.1) stream with 65536 splits in the launch configuration
+    the benchmark times (default tuning), and with every split point used."""
+    spec = synth.c1_spec(W)
+    _say("case c1 full", W)
+    s = spec.generate()
+    blob = rc.encode(s, lanes=W, quant_bits=spec.quant_bits, splits=spec.splits)
+    assert blob.splits == spec.splits
+    plan = rc.Plan(blob)
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    for tuning in ({}, {"waves": 16, "chunk_groups": 8, "units_per_run": 1}):
+        if tuning:
+            plan.set_tuning(**tuning)
+        out = plan.allocate_output()
+        out.fill_(0xA5)
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        plan.decode(ws, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        got = plan.symbols_of(out)
+        assert np.array_equal(got, s), (tuning, int(np.flatnonzero(got != s)[0]))
+        del out
 
 
 def test_single_symbol_stream(rc):
