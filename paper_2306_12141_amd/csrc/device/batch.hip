@@ -24,7 +24,9 @@ template <int W, typename Sym, int K>
 __device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ring0,
                                 uint32_t lane, uint32_t wave, uint32_t waves, uint32_t first, uint32_t count) {
     PairDecoder<W, Sym, K> d(p, lut, ring0, lane);
-    for (uint32_t q = first + wave; q < first + count; q += waves) d.run(q);
+    const uint32_t share = wave < count ? (count - 1 - wave) / waves + 1 : 0u;
+    uint32_t left = share;
+    for (uint32_t q = first + wave; q < first + count; q += waves) d.run(q, --left, share);
 }
 
 template <int K, int WAVES>

@@ -61,14 +61,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
     // Pairs are dealt out by position. The issue arbiter favours older waves,
     // which would leave the youngest waves holding the last pairs of the launch
     // alone (a shared work counter costs more: same-address atomics serialise).
-    // Instead each wave raises its priority the more of its share is left.
+    // Instead each wave's priority follows the part of its share still left.
     const uint32_t share = first < npairs ? (npairs - 1 - first) / stride + 1 : 0u;
     uint32_t left = share;
-    for (uint32_t pair = first; pair < npairs; pair += stride) {
-        --left;
-        set_priority(4 * left / share);
-        d.run(pair);
-    }
+    for (uint32_t pair = first; pair < npairs; pair += stride) d.run(pair, --left, share);
 }
 
 template <typename Sym>

@@ -422,7 +422,12 @@ struct PairDecoder {
         return ok;
     }
 
-    __device__ void run(uint32_t pair) {
+    // Decodes one pair. left: pairs of the wave's share after this one.
+    // The wave's issue priority (0..3) follows the part of its share still to be
+    // decoded, counted in groups with every pair as long as this one and updated
+    // every super-step: the issue arbiter favours older waves, and waves that fall
+    // behind are given precedence so that all end together.
+    __device__ void run(uint32_t pair, uint32_t left, uint32_t share) {
         if (!begin(pair)) return;
         uint32_t kmax = 0, kmin = 0xFFFFFFFFu;
 #pragma unroll
@@ -430,6 +435,12 @@ struct PairDecoder {
             kmax = max(kmax, steps[h]);
             kmin = min(kmin, steps[h]);
         }
+        // level = min(3, floor(4 rem / (share kmax))) with rem = (left + 1) kmax - k;
+        // it drops by one when 4 k exceeds thr.
+        const uint32_t q = share * kmax;
+        uint32_t level = min(3u, 4 * (left + 1) / share);
+        uint32_t thr = 4 * (left + 1) * kmax - level * q;
+        set_priority(level);
         // Synchronisation runs predicated, in half super-steps so that little
         // of the pair does.
         bool ok = true;
@@ -458,9 +469,15 @@ struct PairDecoder {
         for (uint32_t h = 0; h < S; ++h)
             run_on = run_on && res[h] + fq[h] * (int32_t)C >= (int32_t)((kend - k) * W);
         if (run_on) {
-            for (; ok && k < kmax; k += K) ok = super_step<kFast>(k);
+            for (; ok && k < kmax; k += K) {
+                if (4 * k > thr) { --level; thr += q; set_priority(level); }
+                ok = super_step<kFast>(k);
+            }
         } else {
-            for (; ok && k + K <= kmin; k += K) ok = super_step<kFast>(k);
+            for (; ok && k + K <= kmin; k += K) {
+                if (4 * k > thr) { --level; thr += q; set_priority(level); }
+                ok = super_step<kFast>(k);
+            }
             for (; ok && k < kmax; k += K) ok = super_step<kPred>(k);
         }
         if (!ok && lane == 0) atomicOr(p.err, kDevErrUnderflow);
