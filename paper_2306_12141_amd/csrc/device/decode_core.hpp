@@ -354,6 +354,9 @@ struct PairDecoder {
         if (h <= my_ghi) static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
     }
 
+    // Eighths of the share below which priority level L (1..3) ends.
+    __device__ static inline uint32_t prio_cut(uint32_t L) { return L == 3 ? 4u : L == 2 ? 2u : 1u; }
+
     // Bodies of a super-step: unpredicated, synchronisation, fully predicated.
     static constexpr int kFast = 0, kSync = 1, kPred = 2;
 
@@ -423,10 +426,12 @@ struct PairDecoder {
     }
 
     // Decodes one pair. left: pairs of the wave's share after this one.
-    // The wave's issue priority (0..3) follows the part of its share still to be
-    // decoded, counted in groups with every pair as long as this one and updated
-    // every super-step: the issue arbiter favours older waves, and waves that fall
-    // behind are given precedence so that all end together.
+    // The wave's issue priority follows the part of its share still to be
+    // decoded (counted in groups with every pair as long as this one, updated
+    // every super-step): 3 above one half, 2 above a quarter, 1 above an eighth,
+    // else 0. The issue arbiter favours older waves; waves that fall behind are
+    // given precedence so that all end together, and the last level, in which
+    // the oldest wave goes first again, is kept short.
     __device__ void run(uint32_t pair, uint32_t left, uint32_t share) {
         if (!begin(pair)) return;
         uint32_t kmax = 0, kmin = 0xFFFFFFFFu;
@@ -435,11 +440,12 @@ struct PairDecoder {
             kmax = max(kmax, steps[h]);
             kmin = min(kmin, steps[h]);
         }
-        // level = min(3, floor(4 rem / (share kmax))) with rem = (left + 1) kmax - k;
-        // it drops by one when 4 k exceeds thr.
+        // With rem = (left + 1) kmax - k and q = share kmax, level L > 0 holds while
+        // 8 rem >= cut(L) q, i.e. until 8 k exceeds thr = 8 (left + 1) kmax - cut(L) q.
         const uint32_t q = share * kmax;
-        uint32_t level = min(3u, 4 * (left + 1) / share);
-        uint32_t thr = 4 * (left + 1) * kmax - level * q;
+        const uint32_t r8 = 8 * (left + 1);
+        uint32_t level = r8 > 4 * share ? 3u : r8 > 2 * share ? 2u : r8 > share ? 1u : 0u;
+        uint32_t thr = level ? r8 * kmax - prio_cut(level) * q : 0xFFFFFFFFu;
         set_priority(level);
         // Synchronisation runs predicated, in half super-steps so that little
         // of the pair does.
@@ -470,12 +476,20 @@ struct PairDecoder {
             run_on = run_on && res[h] + fq[h] * (int32_t)C >= (int32_t)((kend - k) * W);
         if (run_on) {
             for (; ok && k < kmax; k += K) {
-                if (4 * k > thr) { --level; thr += q; set_priority(level); }
+                if (8 * k > thr) {
+                    --level;
+                    thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
+                    set_priority(level);
+                }
                 ok = super_step<kFast>(k);
             }
         } else {
             for (; ok && k + K <= kmin; k += K) {
-                if (4 * k > thr) { --level; thr += q; set_priority(level); }
+                if (8 * k > thr) {
+                    --level;
+                    thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
+                    set_priority(level);
+                }
                 ok = super_step<kFast>(k);
             }
             for (; ok && k < kmax; k += K) ok = super_step<kPred>(k);
