@@ -108,7 +108,8 @@ typedef struct {
  *                  as one, from the highest unit's split point down to the lowest unit's
  *                  last group (the decoder uses every k-th split point, as combining
  *                  the splits would, Sec. 3.3, without re-packing). 1: every split
- *                  point; 0: chosen at launch, about two runs per resident unit slot. */
+ *                  point; 0: chosen at launch, ceil(M / resident unit slots), i.e. at
+ *                  most one run per unit slot (a wave holds 1 unit, or 2 for W = 32). */
 typedef struct {
     uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu, units_per_run;
 } recoil_tuning;

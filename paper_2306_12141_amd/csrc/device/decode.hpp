@@ -51,10 +51,12 @@ struct DecodeTuning {
     uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0, units_per_run = 0;
 };
 
-// Units per run when the tuning leaves it open: about two runs for every unit
-// slot of the resident grid (slots = resident waves x units per wave).
+// Units per run when the tuning leaves it open: ceil(units / slots), so that
+// every unit slot of the resident grid (resident waves x units per wave) decodes
+// at most one run. Fewer, longer runs pay a unit's fixed costs less often, and
+// with one run per slot no wave holds a second run that others wait for.
 inline uint32_t auto_units_per_run(uint32_t units, uint64_t slots) {
-    const uint64_t k = slots ? units / (2 * slots) : 1;
+    const uint64_t k = slots ? (units + slots - 1) / slots : 1;
     return k < 1 ? 1u : (uint32_t)k;
 }
 
