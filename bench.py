@@ -326,7 +326,8 @@ def run_c3(args, torch, np, rc, synth):
     torch.cuda.synchronize()
     log(f"C3: {batch.items} work items, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
     best, best_ms = batch.autotune(ws, out, err, reps=3)
-    shape = {"waves": best.waves, "chunk_groups": best.chunk_groups, "pairs_per_wave": best.pairs_per_wave}
+    shape = {"waves": best.waves, "chunk_groups": best.chunk_groups, "pairs_per_wave": best.pairs_per_wave,
+             "units_per_run": best.units_per_run}
     log(f"C3: autotuned {shape} ({best_ms:.3f} ms)")
     graph = batch.graph(ws, out, err)
     stream = torch.cuda.current_stream()

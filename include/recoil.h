@@ -104,12 +104,13 @@ typedef struct {
  *                  ring holds 4 K W words (3 K W ring + K W mirror)
  *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)
  *   blocks_per_cu  cap on resident workgroups per CU (0: occupancy limit)
- *   units_per_run  single-stream decode only: k consecutive decode units are decoded
- *                  as one, from the highest unit's split point down to the lowest unit's
- *                  last group (the decoder uses every k-th split point, as combining
- *                  the splits would, Sec. 3.3, without re-packing). 1: every split
- *                  point; 0: chosen at launch, ceil(M / resident unit slots), i.e. at
- *                  most one run per unit slot (a wave holds 1 unit, or 2 for W = 32). */
+ *   units_per_run  k consecutive decode units are decoded as one, from the highest
+ *                  unit's split point down to the lowest unit's last group (the decoder
+ *                  uses every k-th split point, as combining the splits would, Sec. 3.3,
+ *                  without re-packing). 1: every split point. Single-stream decode, 0:
+ *                  chosen at launch, ceil(M / resident unit slots), i.e. at most one run
+ *                  per unit slot (a wave holds 1 unit, or 2 for W = 32). Batched decode
+ *                  (every stream, at most 64): 0 is 1. */
 typedef struct {
     uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu, units_per_run;
 } recoil_tuning;

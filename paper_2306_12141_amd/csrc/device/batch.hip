@@ -63,8 +63,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         p.err = bp.err + wi.stream * bp.err_stride;
         p.n_symbols = d.n_symbols;
         p.units = d.units;
-        p.run = 1;
-        p.runs = d.units;
+        p.run = wi.run > 1 ? wi.run : 1u;
+        p.runs = (d.units + p.run - 1) / p.run;
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
         p.single_symbol = d.single_symbol;

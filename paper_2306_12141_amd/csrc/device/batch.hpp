@@ -21,13 +21,14 @@ struct StreamDesc {
 };
 static_assert(sizeof(StreamDesc) == 64, "StreamDesc is 64 bytes");
 
-// A run of consecutive unit pairs (W = 32) or units (W = 64) of one stream,
-// decoded by one workgroup.
+// Consecutive pairs of one stream, decoded by one workgroup. The stream's
+// units are decoded in runs of `run` consecutive units (Sec. 3.3; 0 or 1: every
+// split point), and a pair is two runs (W = 32) or one (W = 64).
 struct WorkItem {
     uint32_t stream;
-    uint32_t first;     // first pair (W = 32) or unit (W = 64)
+    uint32_t first;     // first pair
     uint32_t count;
-    uint32_t pad;
+    uint32_t run;       // units per run
 };
 
 struct BatchParams {

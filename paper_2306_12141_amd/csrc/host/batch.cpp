@@ -32,13 +32,17 @@ namespace {
 // before each persistent launch.
 constexpr size_t kBatchHeadBytes = 256;
 
-uint32_t pairs_of(const PlanData &pl) {
-    const uint32_t W = pl.blob->lanes, M = pl.blob->splits();
-    return W == 32 ? (M + 1) / 2 : M;
+// Units per run for a stream of M units under tuning value k (0 or 1: one).
+uint32_t run_of(uint32_t M, uint32_t k) { return std::max(1u, std::min(k, std::max(M, 1u))); }
+
+uint32_t pairs_of(const PlanData &pl, uint32_t k) {
+    const uint32_t W = pl.blob->lanes, M = pl.blob->splits(), run = run_of(M, k);
+    const uint32_t runs = (M + run - 1) / run;
+    return W == 32 ? (runs + 1) / 2 : runs;
 }
 
-// Work items: per stream, runs of waves * pairs_per_wave pairs; streams in
-// decreasing size so the longest work starts first.
+// Work items: per stream, waves * pairs_per_wave consecutive pairs each; streams
+// in decreasing size so the longest work starts first.
 void build_items(BatchData &b) {
     b.items.clear();
     std::vector<uint32_t> order(b.plans.size());
@@ -51,15 +55,16 @@ void build_items(BatchData &b) {
     for (uint32_t s : order) {
         const PlanData &pl = b.plans[s];
         if (pl.blob->n_symbols == 0) continue;
-        if (pl.single_symbol) { b.items.push_back({s, 0, 1, 0}); continue; }
-        const uint32_t pairs = pairs_of(pl);
-        for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), 0});
+        if (pl.single_symbol) { b.items.push_back({s, 0, 1, 1}); continue; }
+        const uint32_t run = run_of(pl.blob->splits(), b.tuning.units_per_run);
+        const uint32_t pairs = pairs_of(pl, b.tuning.units_per_run);
+        for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), run});
     }
 }
 
 bool tuning_ok(const recoil_tuning &t) {
     return (t.waves == 8 || t.waves == 16) && (t.chunk_groups == 4 || t.chunk_groups == 8) && t.pairs_per_wave >= 1 &&
-           t.pairs_per_wave <= 64;
+           t.pairs_per_wave <= 64 && t.units_per_run <= 64;
 }
 
 BatchParams params_of(const BatchData &b, void *d_ws, void *d_out, uint32_t *d_err) {
@@ -116,7 +121,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     }
     // Item capacity: the finest tuning (8 waves, one pair per wave).
     size_t cap = 0;
-    for (const PlanData &pl : b.plans) cap += pl.single_symbol ? 1 : (pairs_of(pl) + 7) / 8;
+    for (const PlanData &pl : b.plans) cap += pl.single_symbol ? 1 : (pairs_of(pl, 1) + 7) / 8;
     b.items_cap = std::max<size_t>(cap, 1);
     size_t off = 0;
     b.off_head = off;  off = ws_align(off + kBatchHeadBytes);
@@ -338,11 +343,12 @@ recoil_status recoil_autotune(recoil_batch *batch, void *d_ws, void *d_out, uint
         return fail(RECOIL_ERR_HIP, "autotune: event creation failed");
     recoil_tuning best{};
     float best_t = 1e30f;
-    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, p_opts[] = {1, 2, 4, 8};
+    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, p_opts[] = {1, 2, 4, 8}, r_opts[] = {1, 2, 4};
     for (uint32_t w : waves_opts)
         for (uint32_t k : k_opts)
-            for (uint32_t pp : p_opts) {
-                recoil_tuning t{w, k, pp, 0};
+            for (uint32_t pp : p_opts)
+            for (uint32_t ru : r_opts) {
+                recoil_tuning t{w, k, pp, 0, ru};
                 if (batch_blocks_per_cu(device_tuning(t), b.lut_bytes) < 1) continue;
                 if (recoil_batch_set_tuning(batch, &t, d_ws, stream)) continue;
                 // Warm-up, then the median of `reps` timed launches.

@@ -77,11 +77,12 @@ def test_batch_persistent_and_per_stream(rc, mixed):
     _check_all(batch, out, mixed)
 
 
-@pytest.mark.parametrize("shape", [(16, 4, 1), (16, 4, 2), (8, 4, 4), (8, 8, 1), (8, 8, 8), (16, 8, 2)])
+@pytest.mark.parametrize("shape", [(16, 4, 1), (16, 4, 2), (8, 4, 4), (8, 8, 1), (8, 8, 8), (16, 8, 2),
+                                   (16, 4, 2, 2), (8, 8, 1, 3), (16, 8, 4, 4), (16, 4, 8, 64)])
 def test_batch_shapes(rc, mixed, shape):
     from paper_2306_12141_amd._lib import Tuning
     from paper_2306_12141_amd.batch import Batch
-    batch = Batch([b for _, b in mixed], Tuning(shape[0], shape[1], shape[2], 0))
+    batch = Batch([b for _, b in mixed], Tuning(shape[0], shape[1], shape[2], 0, shape[3] if len(shape) > 3 else 0))
     ws, out, err = batch.allocate()
     batch.upload(ws)
     out.fill_(0x5A)
