@@ -501,8 +501,8 @@ def main():
                     help="first run a plain device copy of BYTES (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build decodes on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not run).", file=sys.stderr)
+        print("bench.py measures one GPU only: the decoder runs on a single MI355X "
+              "(sharding across GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
