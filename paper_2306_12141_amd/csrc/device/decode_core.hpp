@@ -17,16 +17,19 @@
 // its top chunk placed below slot 0, so reads never wrap inside a super-step:
 // word w lives at slot w mod 3C, and positions down to -C read the mirror.
 //
-// Per group the scalar unit only tracks U' += 2 * (count of lanes that did not
-// read) (one s_bcnt0 and one s_lshl1_add per unit); the remaining per-group
-// constant moves into the LDS instructions' immediate offsets of the unrolled
+// Per group the scalar unit only advances the LDS address of the unit's next
+// word by twice the number of reading lanes (one s_bcnt1 and one s_lshl1_add
+// per unit); the per-group store offsets are immediates of the unrolled
 // super-step. The ring read is unconditional and selected with v_cndmask.
 //
 // Synchronisation (Sec. 4.1.1): lane j is switched on with its recorded 16-bit
 // state at the read step of the group its recorded symbol belongs to, just
 // before its first read; groups above the unit's range only advance states.
-// Super-steps holding synchronisation, a ragged last group or the end of a unit
-// run a predicated body; all others the unpredicated one.
+// The synchronisation lead-in runs a predicated body (a lean one when no unit
+// of the pair is the stream's last), and so do a ragged last group and units
+// that end near group 0 or word 0; all other super-steps run the unpredicated
+// body. A run of consecutive units is decoded as one unit from its highest
+// unit's split point (Sec. 3.3).
 #pragma once
 
 #include <type_traits>
@@ -138,8 +141,8 @@ __device__ inline T uni_load(const T *src) {
 // Scalar registers per wave for the decode kernels. A SIMD held eight waves of
 // a kernel using 62 of them but only seven at 76 (measured per-wave start
 // times), and the decode loop needs every wave it can get to hide its LDS
-// latency, so the kernels are compiled to this budget (the few values that do
-// not fit are kept in a VGPR outside the group loops).
+// latency, so the kernels are compiled to this budget (the values that do not
+// fit are kept in VGPR lanes and mostly reloaded outside the group loops).
 #define RECOIL_SGPR_BUDGET 64
 
 template <int W, typename Sym, int K>
