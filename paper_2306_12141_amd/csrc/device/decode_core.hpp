@@ -171,7 +171,7 @@ struct PairDecoder {
     uint32_t presync;      // leading groups of the pair that need the predicated body
     bool sync_lean;        // no unit of the pair is the stream's last (ragged top group, 32-bit states)
     // Per lane.
-    uint32_t x, rec, act;
+    uint32_t x, rec, act, lim;
     uint32_t my_top, my_ghi, my_steps, lane_off;
     bool active;
 
@@ -348,11 +348,17 @@ struct PairDecoder {
     // groups and below the stream's last group: only the switching-on of lanes
     // and the stores of groups above a unit's completion point are predicated.
     // Lanes not yet on decode garbage that is dropped when they switch on.
+    // A lane reads while x < lim, and lim turns from 0 to L when the lane is
+    // switched on, so the read predicate stays a single compare.
     template <uint32_t G_IDX>
     __device__ inline void group_sync(uint32_t k, uint32_t &a, uint32_t &e) {
-        if (k == act) x = rec & 0xFFFFu;
-        read_step<G_IDX>(k >= act && x < kL, a, e);
-        const uint32_t s = T::step(lut, x, n, mask);
+        const bool on = k == act;
+        x = on ? (rec & 0xFFFFu) : x;
+        lim = on ? kL : lim;
+        read_step<G_IDX>(x < lim, a, e);
+        uint32_t lb = lut;
+        asm volatile("" : "+s"(lb));   // the table base as a scalar operand of the address
+        const uint32_t s = T::step(lb, x, n, mask);
         const uint32_t h = my_top - k;
         if (h <= my_ghi) static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
     }
@@ -459,6 +465,7 @@ struct PairDecoder {
         // are) the flag is set for the predicated body of the end.
         const uint32_t lead = (presync + K / 2 - 1) / (K / 2) * (K / 2);
         if (sync_lean && lead <= kmin) {
+            lim = 0;
             for (; ok && k < presync; k += K / 2) ok = super_step<kSync, K / 2>(k);
             active = true;
         } else {
