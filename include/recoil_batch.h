@@ -45,9 +45,12 @@ recoil_status recoil_batch_set_tuning(recoil_batch *batch, const recoil_tuning *
                                       hipStream_t stream);
 recoil_status recoil_batch_get_tuning(const recoil_batch *batch, recoil_tuning *tuning);
 
-/* One persistent launch (a one-thread kernel resets the queue counter in the
- * workspace first). d_out: output base (>= output_bytes); d_error: zeroed device
- * word (RECOIL_DEVERR_* bits). Enqueue-only, capturable. Errors: INVALID_ARG, HIP. */
+/* One persistent launch per decode-table class that has streams (tables up to
+ * 16 KiB, i.e. uint8 with n <= 12; larger tables), each with LDS for its own
+ * class's largest table, in that order; a one-thread kernel resets the class's
+ * queue counter in the workspace before each. d_out: output base (>= output_bytes);
+ * d_error: zeroed device word (RECOIL_DEVERR_* bits). Enqueue-only, capturable.
+ * Errors: INVALID_ARG, HIP. */
 recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_workspace, void *d_out, uint32_t *d_error,
                                   hipStream_t stream);
 
@@ -55,7 +58,7 @@ recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_workspace, 
 recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const void *d_workspace, void *d_out,
                                              uint32_t *d_error, hipStream_t stream);
 
-/* Capture [queue reset; persistent decode] for these buffers in a HIP graph
+/* Capture the [queue reset; persistent decode] pair of every class for these buffers in a HIP graph
  * (captured on a private stream) and instantiate it. Replay with recoil_graph_launch.
  * Errors: INVALID_ARG, HIP. */
 recoil_status recoil_batch_graph_create(const recoil_batch *batch, void *d_workspace, void *d_out, uint32_t *d_error,

@@ -16,21 +16,30 @@
 
 namespace recoil {
 
+// Streams are split into classes by decode-table size, each decoded by a launch of
+// its own whose LDS holds only its class's largest table: a 32 KiB uint16 table
+// would otherwise halve the resident waves of every uint8 stream's launch.
+constexpr uint32_t kBatchClasses = 2;
+constexpr uint32_t kSmallTableBytes = 16384;   // class 0: tables up to 16 KiB (uint8, n <= 12)
+inline uint32_t table_class(size_t lut_bytes) { return lut_bytes <= kSmallTableBytes ? 0u : 1u; }
+
 struct BatchData {
     std::vector<PlanData> plans;
     std::vector<StreamDesc> descs;
-    std::vector<WorkItem> items;
+    std::vector<WorkItem> items;               // class 0's items, then class 1's
     std::vector<uint64_t> out_off, out_bytes;
     size_t off_head = 0, off_descs = 0, off_items = 0, items_cap = 0, total_ws = 0, total_out = 0;
-    uint32_t lut_bytes = 0;
+    uint32_t lut_bytes = 0;                    // largest table of the batch
+    uint32_t cls_lut[kBatchClasses] = {};      // largest table of each class
+    uint32_t cls_begin[kBatchClasses] = {}, cls_count[kBatchClasses] = {};
     recoil_tuning tuning{};
 };
 
 namespace {
 
-// Head section of the batch workspace: the work-queue head, reset by a kernel
-// before each persistent launch.
-constexpr size_t kBatchHeadBytes = 256;
+// Head section of the batch workspace: one work-queue head per class (128 bytes
+// apart), each reset by a kernel before its class's persistent launch.
+constexpr size_t kBatchHeadBytes = 256, kHeadStride = 128;
 
 // Units per run for a stream of M units under tuning value k (0 or 1: one).
 uint32_t run_of(uint32_t M, uint32_t k) { return std::max(1u, std::min(k, std::max(M, 1u))); }
@@ -48,17 +57,28 @@ void build_items(BatchData &b) {
     std::vector<uint32_t> order(b.plans.size());
     for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) {
+        const uint32_t ca = table_class(b.plans[a].lut.size()), cc = table_class(b.plans[c].lut.size());
+        if (ca != cc) return ca < cc;
         return b.plans[a].blob->n_symbols * b.plans[a].blob->symbol_bytes >
                b.plans[c].blob->n_symbols * b.plans[c].blob->symbol_bytes;
     });
     const uint32_t per_item = std::max(1u, b.tuning.waves * b.tuning.pairs_per_wave);
+    for (uint32_t c = 0; c < kBatchClasses; ++c) { b.cls_begin[c] = 0; b.cls_count[c] = 0; b.cls_lut[c] = 0; }
     for (uint32_t s : order) {
         const PlanData &pl = b.plans[s];
         if (pl.blob->n_symbols == 0) continue;
-        if (pl.single_symbol) { b.items.push_back({s, 0, 1, 1}); continue; }
-        const uint32_t run = run_of(pl.blob->splits(), b.tuning.units_per_run);
-        const uint32_t pairs = pairs_of(pl, b.tuning.units_per_run);
-        for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), run});
+        const uint32_t c = table_class(pl.lut.size());
+        if (b.cls_count[c] == 0) b.cls_begin[c] = (uint32_t)b.items.size();
+        b.cls_lut[c] = std::max<uint32_t>(b.cls_lut[c], (uint32_t)pl.lut.size());
+        const size_t before = b.items.size();
+        if (pl.single_symbol) {
+            b.items.push_back({s, 0, 1, 1});
+        } else {
+            const uint32_t run = run_of(pl.blob->splits(), b.tuning.units_per_run);
+            const uint32_t pairs = pairs_of(pl, b.tuning.units_per_run);
+            for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), run});
+        }
+        b.cls_count[c] += (uint32_t)(b.items.size() - before);
     }
 }
 
@@ -67,21 +87,39 @@ bool tuning_ok(const recoil_tuning &t) {
            t.pairs_per_wave <= 64 && t.units_per_run <= 64;
 }
 
-BatchParams params_of(const BatchData &b, void *d_ws, void *d_out, uint32_t *d_err) {
+BatchTuning device_tuning(const recoil_tuning &t) { return BatchTuning{t.waves, t.chunk_groups, t.blocks_per_cu}; }
+
+BatchParams params_of(const BatchData &b, uint32_t cls, void *d_ws, void *d_out, uint32_t *d_err) {
     BatchParams bp{};
     unsigned char *ws = static_cast<unsigned char *>(d_ws);
     bp.ws = ws;
     bp.out = static_cast<unsigned char *>(d_out);
     bp.streams = reinterpret_cast<const StreamDesc *>(ws + b.off_descs);
-    bp.items = reinterpret_cast<const WorkItem *>(ws + b.off_items);
-    bp.head = reinterpret_cast<uint32_t *>(ws + b.off_head);
+    bp.items = reinterpret_cast<const WorkItem *>(ws + b.off_items) + b.cls_begin[cls];
+    bp.head = reinterpret_cast<uint32_t *>(ws + b.off_head + cls * kHeadStride);
     bp.err = d_err;
-    bp.n_items = (uint32_t)b.items.size();
-    bp.lut_bytes = b.lut_bytes;
+    bp.n_items = b.cls_count[cls];
+    bp.lut_bytes = b.cls_lut[cls];
     return bp;
 }
 
-BatchTuning device_tuning(const recoil_tuning &t) { return BatchTuning{t.waves, t.chunk_groups, t.blocks_per_cu}; }
+// One persistent launch per table class that has work, in class order.
+hipError_t launch_classes(const BatchData &b, void *d_ws, void *d_out, uint32_t *d_err, hipStream_t stream) {
+    for (uint32_t c = 0; c < kBatchClasses; ++c) {
+        if (b.cls_count[c] == 0) continue;
+        hipError_t e = launch_batch(params_of(b, c, d_ws, d_out, d_err), device_tuning(b.tuning), stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Launch shape fits the CU for every class that has work.
+bool shape_fits(const BatchData &b, const recoil_tuning &t) {
+    for (uint32_t c = 0; c < kBatchClasses; ++c)
+        if (b.cls_count[c] && batch_blocks_per_cu(device_tuning(t), b.cls_lut[c]) < 1) return false;
+    return true;
+}
+
 
 std::mutex g_tune_mu;
 std::map<std::string, recoil_tuning> g_tune_cache;
@@ -230,7 +268,7 @@ recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_ws, void *d
     using namespace recoil;
     if (!batch || !d_ws || !d_out || !d_error) return fail(RECOIL_ERR_INVALID_ARG, "decode_batch: bad arguments");
     const BatchData &b = batch->d;
-    hipError_t e = launch_batch(params_of(b, d_ws, d_out, d_error), device_tuning(b.tuning), stream);
+    hipError_t e = launch_classes(b, d_ws, d_out, d_error, stream);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch: ") + hipGetErrorString(e));
     return RECOIL_OK;
 }
@@ -277,7 +315,7 @@ recoil_status recoil_batch_graph_create(const recoil_batch *batch, void *d_ws, v
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         const BatchData &b = batch->d;
-        hipError_t le = launch_batch(params_of(b, d_ws, d_out, d_error), device_tuning(b.tuning), cs);
+        hipError_t le = launch_classes(b, d_ws, d_out, d_error, cs);
         e = hipStreamEndCapture(cs, &g->graph);
         if (le != hipSuccess) e = le;
     }
@@ -349,7 +387,7 @@ recoil_status recoil_autotune(recoil_batch *batch, void *d_ws, void *d_out, uint
             for (uint32_t pp : p_opts)
             for (uint32_t ru : r_opts) {
                 recoil_tuning t{w, k, pp, 0, ru};
-                if (batch_blocks_per_cu(device_tuning(t), b.lut_bytes) < 1) continue;
+                if (!shape_fits(b, t)) continue;
                 if (recoil_batch_set_tuning(batch, &t, d_ws, stream)) continue;
                 // Warm-up, then the median of `reps` timed launches.
                 if (recoil_decode_batch(batch, d_ws, d_out, d_error, stream)) continue;
