@@ -313,7 +313,7 @@ struct PairDecoder {
             asm volatile("" : "+v"(t));                             // keep v_lshl_add + v_mad_u32_u24
             addr = __umul24(upper, d) + t;
             a = a_next;
-            e += 2u * (uint32_t)__builtin_popcount(bh);
+            e = s_lshl1_add((uint32_t)__builtin_popcount(bh), e);
         }
         uint32_t w = lds_ld<uint16_t>(addr);
         // Keep the read unconditional: lanes that do not need it read an in-ring word and drop it.
