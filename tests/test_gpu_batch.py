@@ -92,6 +92,25 @@ def test_batch_shapes(rc, mixed, shape):
     _check_all(batch, out, mixed)
 
 
+@pytest.mark.parametrize("width", [np.uint8, np.uint16])
+def test_batch_one_table_class(rc, mixed, width):
+    """A batch whose streams all fall in one decode-table class (the other class's
+    launch is skipped), in a graph replayed twice."""
+    from paper_2306_12141_amd.batch import Batch
+    sel = [(s, b) for s, b in mixed if s.dtype == width]
+    assert len(sel) >= 4
+    batch = Batch([b for _, b in sel])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    g = batch.graph(ws, out, err)
+    for rep in range(2):
+        out.fill_(0xA5 if rep else 0x5A)
+        g.launch()
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        _check_all(batch, out, sel)
+
+
 def test_graph_replays(rc, mixed):
     """The captured graph replays several times, with eager work in between;
     each replay must equal the eager result."""
