@@ -235,6 +235,38 @@ def test_size_against_entropy(orc, c0):
     assert 16 * hdr["B"] / len(s) < h * 1.01 + 0.01
 
 
+# Def. 4.1 on closed-form streams, worked by hand. With f = 1 at n = 8 lane j
+# emits one word before each of its local symbols 1, 3, 5, ... (0-based), i.e.
+# in the odd groups m, lanes in increasing order, so word w belongs to group
+# m = 2 floor(w / W) + 1 and lane j = w mod W, and records the lane's previous
+# symbol, index (m - 1) W + j (the event attribution of the worked example).
+# Word w is usable once every lane has an event. At word w: Imax = (m - 1) W + j;
+# Imin = (m - 1) W if j = W - 1, else (m - 3) W + j + 1 (lane j + 1's event of
+# the previous odd group). For W = 2: Imax = 4 floor(w/2) + j, t_s = Imax - Imin + 1
+# = 2 (j = 1) or 4 (j = 0), and for the first split t = Imax + 1.
+#   N = 40, two units, T = 20:  j = 1: H = |4q + 2 - 20| + |4q - 20| -> 2 at q = 5;
+#                                j = 0: H = |4q - 19| + |4q - 23|     -> >= 4.
+#   so the split is word 11 (Imax 21, Imin 20).
+#   N = 60, three units: first T = 20 -> word 11 again; then T = ceil(38 / 2) = 19 and
+#   t = Imax - 21: j = 1: H = |4q - 39| + |4q - 41| -> 2 at q = 10 (word 21, Imax 41);
+#   j = 0: H = |4q - 40| + |4q - 44| -> >= 4.
+# For W = 1 every event is its own lane's only one: word w has Imax = Imin = 2w,
+# t_s = 1, t = 2w + 1; N = 40, T = 20: H = |2w - 19| + |2w - 20| -> 1 at w = 10.
+@pytest.mark.parametrize("lanes,N,units,expect", [
+    (2, 40, 2, [(11, 21, 20)]),
+    (2, 60, 3, [(11, 21, 20), (21, 41, 40)]),
+    (1, 40, 2, [(10, 20, 20)]),
+])
+def test_heuristic_hand_worked(orc, lanes, N, units, expect):
+    s = _rng_symbols(21 + N, N, 256)
+    p = orc.params(lanes=lanes, quant_bits=8, alphabet=256)
+    enc = orc.encode(s, p, units, freq=np.ones(256, dtype=np.uint32))
+    assert enc.threads == units
+    got = [(enc.split(k).pos, enc.split(k).imax, enc.split(k).imin) for k in range(1, units)]
+    assert got == expect
+    assert np.array_equal(orc.Decoder(enc.container()).all(), s)
+
+
 def test_heuristic_properties(orc, c0):
     spec, s, p, enc, c = c0
     dec = orc.Decoder(c)
