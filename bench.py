@@ -124,6 +124,26 @@ def time_decode(plan, ws, out, err, steps, warmup, torch):
             "settle_launches": settled}
 
 
+def time_cold(plan, ws, out, err, torch, reps=9, evict_bytes=1 << 30):
+    """Single decodes, each right after reading `evict_bytes` of other device memory
+    (evicts the last-level cache without leaving dirty lines): how much the timed
+    back-to-back decodes gain from the cache keeping part of the stream."""
+    junk = torch.ones(evict_bytes // 8, dtype=torch.int64, device="cuda")
+    per = []
+    for _ in range(reps):
+        junk.sum()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.decode(ws, out, err)
+        b.record()
+        torch.cuda.synchronize()
+        per.append(a.elapsed_time(b))
+    del junk
+    per.sort()
+    return {"median_ms": round(per[len(per) // 2], 5), "min_ms": round(per[0], 5), "evicted_bytes": evict_bytes,
+            "how": "one decode after reading the evicted bytes, HIP events around the decode"}
+
+
 def check_exact(plan, out, symbols, err, np):
     got = plan.symbols_of(out)
     ok = bool(np.array_equal(got, symbols)) and int(err.item()) == 0
@@ -210,6 +230,9 @@ def run_c1(args, torch, np, rc, synth):
         "shape": {"blocks": shape.blocks, "waves_per_block": shape.waves_per_block,
                   "units_per_run": shape.units_per_run, "runs": shape.runs},
     }
+    if not args.no_extras:
+        result["cache_cold"] = time_cold(plan, ws, out, err, torch)
+        log(f"W={lanes} after evicting the caches: {result['cache_cold']['median_ms']:.4f} ms")
     if not args.no_extras and shape.units_per_run != 1:
         # The same decode using every split point (one run per unit).
         kg = int(args.shape.split(",")[1]) if args.shape else 8
@@ -531,6 +554,8 @@ def main():
                          "pcie_inclusive_decoded_gbs": round(base["pcie_inclusive_gbs"], 2)}}
     if "every_split_point" in base:
         extras["every_split_point"] = base["every_split_point"]
+    if "cache_cold" in base:
+        extras["cache_cold"] = base["cache_cold"]
     if not args.no_extras:
         # The same stream interleaved the other way (the workload names both), and
         # the split-count sweep on the W = 32 encoding.
