@@ -198,6 +198,17 @@ size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
  * units_per_run 0). pairs_per_wave is ignored.
  * Errors: INVALID_ARG (unsupported shape). */
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *tuning);
+/* Autotuner for one plan: times every launch shape (waves per workgroup 8/16 x
+ * K 4/8 x units per run 0/1/2/4) with recoil_decode on the caller's buffers,
+ * `reps` timed launches each after one warm-up, keeps the fastest median and
+ * leaves it set on the plan. Results are cached per process, keyed by the
+ * device architecture and the stream's shape (N, M, W, symbol bytes, n).
+ * Synchronises `stream`; d_out and d_error receive the last trial's decode.
+ * best (may be NULL) receives the tuning (pairs_per_wave is 1); best_ms (may be
+ * NULL) the winning median, or -1 when served from the cache.
+ * Errors: INVALID_ARG, HIP. */
+recoil_status recoil_plan_autotune(recoil_plan *plan, void *d_workspace, void *d_out, uint32_t *d_error,
+                                   hipStream_t stream, uint32_t reps, recoil_tuning *best, float *best_ms);
 /* The grid and runs recoil_decode would use on the current device (all zero
  * when no decode kernel runs: empty or single-symbol streams). Launches nothing.
  * Errors: INVALID_ARG, HIP (occupancy query failed). */

@@ -142,6 +142,16 @@ class Plan:
         t = _lib.Tuning(waves, chunk_groups, 1, blocks_per_cu, units_per_run)
         check(_lib.recoil_plan_set_tuning(self._h, C.byref(t)), "recoil_plan_set_tuning")
 
+    def autotune(self, workspace, out, err, reps: int = 3, stream=None):
+        """Time the launch shapes on these buffers and keep the fastest (cached per
+        device and stream shape). Returns (tuning, median ms or -1 if cached)."""
+        best = _lib.Tuning()
+        ms = C.c_float()
+        check(_lib.recoil_plan_autotune(self._h, C.c_void_p(workspace.data_ptr()), C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(err.data_ptr()), _stream_handle(stream), reps, C.byref(best),
+                                        C.byref(ms)), "recoil_plan_autotune")
+        return best, ms.value
+
     def shape(self) -> _lib.DecodeShape:
         """Grid and runs recoil_decode uses for this plan on the current device."""
         sh = _lib.DecodeShape()

@@ -84,6 +84,7 @@ class DecodeShape(C.Structure):
 
 recoil_plan_set_tuning = _sig("recoil_plan_set_tuning", [P, C.POINTER(Tuning)])
 recoil_plan_shape = _sig("recoil_plan_shape", [P, C.POINTER(DecodeShape)])
+recoil_plan_autotune = _sig("recoil_plan_autotune", [P, P, P, P, P, u32, C.POINTER(Tuning), C.POINTER(C.c_float)])
 recoil_default_tuning = _sig("recoil_default_tuning", [], Tuning)
 recoil_batch_create = _sig("recoil_batch_create", [P, u32, C.POINTER(Tuning), C.POINTER(P), C.POINTER(sz),
                                                    C.POINTER(sz)])

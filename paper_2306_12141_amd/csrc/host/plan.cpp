@@ -3,7 +3,11 @@
 // launch the decode kernels.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -277,6 +281,80 @@ recoil_status recoil_plan_shape(const recoil_plan *plan, recoil_decode_shape *ou
                                  pl.tuning, nullptr, &sh);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_shape: ") + hipGetErrorString(e));
     *out = recoil_decode_shape{sh.blocks, sh.waves, sh.units_per_run, sh.runs};
+    return RECOIL_OK;
+}
+
+namespace {
+std::mutex g_plan_tune_mu;
+std::map<std::string, recoil::DecodeTuning> g_plan_tune_cache;
+}  // namespace
+
+recoil_status recoil_plan_autotune(recoil_plan *plan, void *d_ws, void *d_out, uint32_t *d_error, hipStream_t stream,
+                                   uint32_t reps, recoil_tuning *best_out, float *best_ms) {
+    using namespace recoil;
+    if (!plan || !d_ws || !d_error || reps == 0 || (!d_out && plan->d.blob->n_symbols))
+        return fail(RECOIL_ERR_INVALID_ARG, "plan_autotune: bad arguments");
+    PlanData &pl = plan->d;
+    const BlobData &b = *pl.blob;
+    auto report = [&](const DecodeTuning &t, float ms) {
+        if (best_out) *best_out = recoil_tuning{t.waves, t.chunk_groups, 1, t.blocks_per_cu, t.units_per_run};
+        if (best_ms) *best_ms = ms;
+    };
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    const std::string key = std::string(prop.gcnArchName) + "/" + std::to_string(b.n_symbols) + "/" +
+                            std::to_string(b.splits()) + "/" + std::to_string(b.lanes) + "/" +
+                            std::to_string(b.symbol_bytes) + "/" + std::to_string(b.quant_bits);
+    {
+        std::lock_guard<std::mutex> lk(g_plan_tune_mu);
+        auto it = g_plan_tune_cache.find(key);
+        if (it != g_plan_tune_cache.end()) {
+            pl.tuning = it->second;
+            report(it->second, -1.0f);
+            return RECOIL_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RECOIL_ERR_HIP, "plan_autotune: event creation failed");
+    const DecodeTuning saved = pl.tuning;
+    DecodeTuning best = saved;
+    float best_t = 1e30f;
+    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, run_opts[] = {0, 1, 2, 4};
+    for (uint32_t w : waves_opts)
+        for (uint32_t k : k_opts)
+            for (uint32_t r : run_opts) {
+                pl.tuning = DecodeTuning{w, k, 0, r};
+                // One warm-up launch, then the median of `reps` timed launches.
+                if (recoil_decode(plan, d_ws, d_out, d_error, stream)) continue;
+                std::vector<float> ts;
+                for (uint32_t i = 0; i < reps; ++i) {
+                    (void)hipEventRecord(e0, stream);
+                    (void)recoil_decode(plan, d_ws, d_out, d_error, stream);
+                    (void)hipEventRecord(e1, stream);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ts.push_back(ms);
+                }
+                std::sort(ts.begin(), ts.end());
+                const float med = ts[ts.size() / 2];
+                if (med < best_t) { best_t = med; best = pl.tuning; }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_t >= 1e30f) {
+        pl.tuning = saved;
+        return fail(RECOIL_ERR_HIP, "plan_autotune: no configuration ran");
+    }
+    pl.tuning = best;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_tune_mu);
+        g_plan_tune_cache[key] = best;
+    }
+    report(best, best_t);
     return RECOIL_OK;
 }
 

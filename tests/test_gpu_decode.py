@@ -143,6 +143,30 @@ def test_units_per_run_shape(rc):
     assert sh.runs <= sh.blocks * sh.waves_per_block           # W = 64: one unit slot per wave
 
 
+def test_plan_autotune(rc):
+    """The single-stream autotuner leaves a valid shape on the plan, the decode with it
+    is exact, and a second plan of the same shape is served from the cache."""
+    s = _syms(55, 1 << 20, 256, np.uint8, 1.1)
+    blob = rc.encode(s, lanes=64, quant_bits=12, splits=2048)
+    plan = rc.Plan(blob)
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    best, ms = plan.autotune(ws, out, err, reps=2)
+    assert best.waves in (8, 16) and best.chunk_groups in (4, 8) and best.units_per_run in (0, 1, 2, 4)
+    assert ms > 0
+    out.fill_(0x3C)
+    err.zero_()
+    plan.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and np.array_equal(plan.symbols_of(out), s)
+    plan2 = rc.Plan(blob)
+    best2, ms2 = plan2.autotune(ws, out, err, reps=2)
+    assert ms2 == -1.0 and (best2.waves, best2.chunk_groups, best2.units_per_run) == \
+        (best.waves, best.chunk_groups, best.units_per_run)
+
+
 def test_random_split_sets_runs(rc, orc):
     """Irregular oracle-built split sets decoded in runs of 2 and 3 units."""
     from tests import _fmt
