@@ -115,9 +115,11 @@ typedef struct {
     uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu, units_per_run;
 } recoil_tuning;
 
-/* Grid of a single-stream decode and the runs it decodes (recoil_plan_shape). */
+/* Grid of a single-stream decode and the runs it decodes (recoil_plan_shape).
+ * units_per_wave: runs decoded side by side in one wave: 1 for W = 64; for W = 32,
+ * 2 (one per half-wave), or 1 when every run has a wave of its own. */
 typedef struct {
-    uint32_t blocks, waves_per_block, units_per_run, runs;
+    uint32_t blocks, waves_per_block, units_per_run, runs, units_per_wave;
 } recoil_decode_shape;
 
 typedef struct recoil_blob recoil_blob;   /* immutable encoded stream; safe to share between threads */

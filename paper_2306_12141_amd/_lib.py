@@ -79,7 +79,8 @@ class Tuning(C.Structure):
 
 
 class DecodeShape(C.Structure):
-    _fields_ = [("blocks", u32), ("waves_per_block", u32), ("units_per_run", u32), ("runs", u32)]
+    _fields_ = [("blocks", u32), ("waves_per_block", u32), ("units_per_run", u32), ("runs", u32),
+                ("units_per_wave", u32)]
 
 
 recoil_plan_set_tuning = _sig("recoil_plan_set_tuning", [P, C.POINTER(Tuning)])

@@ -39,10 +39,13 @@ namespace {
 
 using namespace dev;
 
-template <int W, typename Sym, int K, int WAVES>
+// SS: units per wave. W = 32 runs two units per wave (one per half-wave), or,
+// when the stream has no more units than the grid has waves, one unit per wave
+// with the upper half-wave switched off: then twice as many waves decode.
+template <int W, typename Sym, int K, int WAVES, int SS = 64 / W>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET))) void decode_units(
     DecodeParams p) {
-    using D = PairDecoder<W, Sym, K>;
+    using D = PairDecoder<W, Sym, K, SS>;
     using L = Lds<0, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
@@ -55,6 +58,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
     __syncthreads();
     const uint32_t wave = uni(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
+    if (W * SS < 64 && lane >= (uint32_t)(W * SS)) return;   // lanes without a coder (no barrier follows)
     const uint32_t npairs = (p.runs + D::S - 1) / D::S;
     const uint32_t first = blockIdx.x * WAVES + wave, stride = gridDim.x * WAVES;
     D d(p, base + L::TABLE, base + L::PAD + wave * L::WAVE_LDS, lane);
@@ -88,35 +92,57 @@ size_t lds_bytes(uint32_t quant_bits) {
     return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
 }
 
-template <int W, typename Sym, int K, int WAVES>
+template <int W, typename Sym, int K, int WAVES, int SS>
 int units_occupancy(uint32_t quant_bits) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES>, 64 * WAVES,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS>, 64 * WAVES,
                                                      lds_bytes<W, Sym, K, WAVES>(quant_bits)) != hipSuccess)
         return 0;
     return per_cu;
 }
 
-template <int W, typename Sym, int K, int WAVES>
-hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
-    int per_cu = units_occupancy<W, Sym, K, WAVES>(p.quant_bits);
-    if (per_cu < 1) return hipErrorInvalidConfiguration;
+// Resident workgroups of the kernel with SS units per wave (0: does not fit).
+template <int W, typename Sym, int K, int WAVES, int SS>
+uint32_t resident_blocks(const DecodeParams &p, const DecodeTuning &t) {
+    int per_cu = units_occupancy<W, Sym, K, WAVES, SS>(p.quant_bits);
+    if (per_cu < 1) return 0;
     if (t.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)t.blocks_per_cu);
-    const uint32_t resident = (uint32_t)(device_cus() * per_cu);
+    return (uint32_t)(device_cus() * per_cu);
+}
+
+template <int W, typename Sym, int K, int WAVES, int SS>
+hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resident, hipStream_t stream,
+                     DecodeShape *shape) {
     DecodeParams q = p;
-    q.run = t.units_per_run ? t.units_per_run : auto_units_per_run(p.units, (uint64_t)resident * WAVES * (64 / W));
+    q.run = t.units_per_run ? t.units_per_run : auto_units_per_run(p.units, (uint64_t)resident * WAVES * SS);
     q.run = std::min(q.run, std::max(p.units, 1u));
     q.runs = (uint32_t)(((uint64_t)p.units + q.run - 1) / q.run);
-    const uint32_t pairs = (q.runs + 64 / W - 1) / (64 / W);
+    const uint32_t pairs = (q.runs + SS - 1) / SS;
     const uint32_t need = (pairs + WAVES - 1) / WAVES;
     const uint32_t blocks = std::max<uint32_t>(1u, std::min<uint32_t>(need, resident));
     if (shape) {
-        *shape = DecodeShape{blocks, (uint32_t)WAVES, q.run, q.runs};
+        *shape = DecodeShape{blocks, (uint32_t)WAVES, q.run, q.runs, (uint32_t)SS};
         return hipSuccess;
     }
     const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits);
-    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
     return hipGetLastError();
+}
+
+template <int W, typename Sym, int K, int WAVES>
+hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
+    if constexpr (W == 32) {
+        // One unit per wave when every run then has a wave of its own: the
+        // pair kernel would leave half of those waves idle.
+        const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1>(p, t);
+        const uint64_t slots = (uint64_t)rs * WAVES;
+        const uint32_t k = t.units_per_run ? std::min(t.units_per_run, std::max(p.units, 1u)) : 1u;
+        const uint64_t runs = ((uint64_t)p.units + k - 1) / k;
+        if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1>(p, t, rs, stream, shape);
+    }
+    const uint32_t resident = resident_blocks<W, Sym, K, WAVES, 64 / W>(p, t);
+    if (resident == 0) return hipErrorInvalidConfiguration;
+    return launch_ss<W, Sym, K, WAVES, 64 / W>(p, t, resident, stream, shape);
 }
 
 template <int W, typename Sym>
@@ -132,7 +158,7 @@ hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_
 
 hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
                          hipStream_t stream, DecodeShape *shape) {
-    if (shape) *shape = DecodeShape{0, 0, 0, 0};
+    if (shape) *shape = DecodeShape{0, 0, 0, 0, 0};
     if (p.n_symbols == 0) return hipSuccess;
     if (p.single_symbol) {
         if (shape) return hipSuccess;

@@ -62,7 +62,7 @@ inline uint32_t auto_units_per_run(uint32_t units, uint64_t slots) {
 
 // Grid of a single-stream launch and the runs it decodes.
 struct DecodeShape {
-    uint32_t blocks, waves, units_per_run, runs;
+    uint32_t blocks, waves, units_per_run, runs, units_per_wave;
 };
 
 // Launcher (decode.hip). Returns hipSuccess or the launch error. With shape

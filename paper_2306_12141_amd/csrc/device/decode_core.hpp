@@ -84,9 +84,9 @@ struct Table<uint16_t> {
     }
 };
 
-template <int W, int K>
+template <int W, int K, int SS = 64 / W>
 struct Geo {
-    static constexpr uint32_t S = 64 / W;             // units per wave
+    static constexpr uint32_t S = SS;                 // units per wave (W = 32: one per half-wave, or one)
     static constexpr uint32_t C = K * W;              // chunk words
     static constexpr uint32_t R = 3 * C;              // ring slots
     static constexpr uint32_t UNIT = 2 * (C + R);     // LDS bytes per unit: mirror + ring
@@ -145,9 +145,9 @@ __device__ inline T uni_load(const T *src) {
 // fit are kept in VGPR lanes and mostly reloaded outside the group loops).
 #define RECOIL_SGPR_BUDGET 64
 
-template <int W, typename Sym, int K>
+template <int W, typename Sym, int K, int SS = 64 / W>
 struct PairDecoder {
-    using G = Geo<W, K>;
+    using G = Geo<W, K, SS>;
     using T = Table<Sym>;
     using Chunk = typename G::Chunk;
     static constexpr uint32_t S = G::S, C = G::C, R = G::R;
@@ -178,7 +178,7 @@ struct PairDecoder {
     __device__ PairDecoder(const DecodeParams &p_, uint32_t lut_, uint32_t ring0_, uint32_t lane_)
         : p(p_), lut(lut_), ring0(ring0_), lane(lane_) {
         col = lane & (W - 1);
-        upper = (W == 32) ? (lane >> 5) : 0u;
+        upper = (S == 2) ? (lane >> 5) : 0u;
         coder = W - 1 - col;
         n = p.quant_bits;
         mask = (1u << n) - 1u;
@@ -300,9 +300,9 @@ struct PairDecoder {
         // The lane's word is m words above the unit's top word (descending ring).
         // a/e stay opaque SGPR byte addresses so each address is one v_lshl_add.
         asm volatile("" : "+s"(a));
-        if constexpr (W == 32) asm volatile("" : "+s"(e));
+        if constexpr (S == 2) asm volatile("" : "+s"(e));
         uint32_t addr;
-        if constexpr (W == 64) {
+        if constexpr (S == 1) {
             addr = (m << 1) + a;
             a = s_lshl1_add((uint32_t)__builtin_popcountll(bal), a);
         } else {

@@ -280,7 +280,7 @@ recoil_status recoil_plan_shape(const recoil_plan *plan, recoil_decode_shape *ou
     hipError_t e = launch_decode(decode_params(pl, nullptr, nullptr, nullptr), pl.blob->lanes, pl.blob->symbol_bytes,
                                  pl.tuning, nullptr, &sh);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_shape: ") + hipGetErrorString(e));
-    *out = recoil_decode_shape{sh.blocks, sh.waves, sh.units_per_run, sh.runs};
+    *out = recoil_decode_shape{sh.blocks, sh.waves, sh.units_per_run, sh.runs, sh.units_per_wave};
     return RECOIL_OK;
 }
 
