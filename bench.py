@@ -228,7 +228,7 @@ def run_c1(args, torch, np, rc, synth):
         "upload_bytes": plan.device_bytes,
         "pcie_inclusive_gbs": out_bytes / (upload_s + t["kernel_ms_mean"] * 1e-3) / 1e9,
         "shape": {"blocks": shape.blocks, "waves_per_block": shape.waves_per_block,
-                  "units_per_run": shape.units_per_run, "runs": shape.runs},
+                  "units_per_run": shape.units_per_run, "runs": shape.runs, "units_per_wave": shape.units_per_wave},
     }
     if not args.no_extras:
         result["cache_cold"] = time_cold(plan, ws, out, err, torch)
@@ -267,8 +267,10 @@ def run_c0(args, torch, np, rc, synth):
     exact = check_exact(plan, out, s, err, np)
     gbs = len(s) / (t["ms_per_step"] * 1e-3) / 1e9
     log(f"C0: {t['ms_per_step']:.4f} ms/step, {gbs:.1f} GB/s, exact={exact}")
+    sh = plan.shape()
     return {"decoded_gbs": round(gbs, 2), "ms_per_step": round(t["ms_per_step"], 5), "exact": exact,
-            "splits": blob.info.splits, "metadata_bytes": blob.info.metadata_bytes}
+            "splits": blob.info.splits, "metadata_bytes": blob.info.metadata_bytes, "runs": sh.runs,
+            "units_per_wave": sh.units_per_wave}
 
 
 def run_combined(args, base, torch, np, rc):
@@ -286,7 +288,9 @@ def run_combined(args, base, torch, np, rc):
         t = time_decode(plan, ws, out, err, max(3, args.steps // 2), 2, torch)
         exact = check_exact(plan, out, s, err, np)
         gbs = len(s) / (t["ms_per_step"] * 1e-3) / 1e9
-        rows.append({"splits": info.splits, "runs": plan.shape().runs, "metadata_bytes": info.metadata_bytes,
+        sh = plan.shape()
+        rows.append({"splits": info.splits, "runs": sh.runs, "units_per_wave": sh.units_per_wave,
+                     "metadata_bytes": info.metadata_bytes,
                      "transferred_bytes": info.total_bytes, "decoded_gbs": round(gbs, 2),
                      "ms": round(t["ms_per_step"], 4), "exact": exact})
         log(f"combined to {info.splits}: meta {info.metadata_bytes} B, {gbs:.1f} GB/s, exact={exact}")
