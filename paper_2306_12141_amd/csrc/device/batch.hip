@@ -118,12 +118,7 @@ int occupancy(uint32_t lut_bytes) {
 
 template <int K, int WAVES>
 hipError_t launch(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t stream) {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
-    }
+    const int cus = device_cus();
     int per_cu = occupancy<K, WAVES>(bp.lut_bytes);
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     if (blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)blocks_per_cu);

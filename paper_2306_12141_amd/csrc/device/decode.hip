@@ -30,6 +30,7 @@
 // Super-steps that contain synchronisation, the partial last group or the end
 // of a unit run a predicated body; all others run the unpredicated one.
 #include <algorithm>
+#include <atomic>
 
 #include "decode_core.hpp"
 
@@ -74,17 +75,6 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
 template <typename Sym>
 __global__ __launch_bounds__(256) void fill_symbol(Sym *out, uint64_t n, Sym v) {
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) out[i] = v;
-}
-
-int device_cus() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 1;
-    }
-    return cus;
 }
 
 template <int W, typename Sym, int K, int WAVES>
@@ -155,6 +145,21 @@ hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_
 }
 
 }  // namespace
+
+int device_cus() {
+    constexpr int kCached = 64;
+    static std::atomic<int> cached[kCached];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (dev >= 0 && dev < kCached) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 1;
+    if (dev >= 0 && dev < kCached) cached[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
 
 hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_bytes, const DecodeTuning &t,
                          hipStream_t stream, DecodeShape *shape) {

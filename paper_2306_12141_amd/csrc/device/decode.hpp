@@ -65,6 +65,9 @@ struct DecodeShape {
     uint32_t blocks, waves, units_per_run, runs, units_per_wave;
 };
 
+// Compute units of the current device (at least 1), cached per device.
+int device_cus();
+
 // Launcher (decode.hip). Returns hipSuccess or the launch error. With shape
 // non-null nothing is launched: the grid and runs a launch would use are
 // stored there (all zero when no decode kernel would run).
