@@ -110,7 +110,9 @@ typedef struct {
  *                  without re-packing). 1: every split point. Single-stream decode, 0:
  *                  chosen at launch, ceil(M / resident unit slots), i.e. at most one run
  *                  per unit slot (a wave holds 1 unit, or 2 for W = 32). Batched decode
- *                  (every stream, at most 64): 0 is 1. */
+ *                  (at most 64; 0 is 1): every stream's run length, shortened to
+ *                  ceil(M / (waves x units per wave)) for a stream whose M units would
+ *                  otherwise leave waves of its workgroup without a run. */
 typedef struct {
     uint32_t waves, chunk_groups, pairs_per_wave, blocks_per_cu, units_per_run;
 } recoil_tuning;

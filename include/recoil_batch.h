@@ -68,7 +68,7 @@ void recoil_graph_free(recoil_graph *graph);
 
 /*
  * Autotuner: times every launch shape (waves 8/16 x K 4/8 x pairs per wave
- * 1/2/4/8 x units per run 1/2/4, shapes that do not fit the CU skipped) on this batch, `reps` timed
+ * 1/2/4/8 x units per run 1/2/4/8, shapes that do not fit the CU skipped) on this batch, `reps` timed
  * launches each after one warm-up, keeps the fastest median and leaves it set on
  * the batch (work items re-uploaded). Results are cached per process, keyed by the
  * device architecture and the batch's shape. Synchronises `stream`.

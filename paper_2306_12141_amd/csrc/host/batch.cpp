@@ -50,6 +50,17 @@ uint32_t pairs_of(const PlanData &pl, uint32_t k) {
     return W == 32 ? (runs + 1) / 2 : runs;
 }
 
+// Units per run of one stream: the tuned length, shortened for a stream with too
+// few units to give each unit slot of a workgroup (waves x units per wave) a run
+// of that length, so that its units spread over the waves instead of leaving
+// some idle while others decode long runs.
+uint32_t stream_run(const PlanData &pl, const recoil_tuning &t) {
+    const uint32_t M = pl.blob->splits();
+    const uint32_t slots = std::max(1u, t.waves * (pl.blob->lanes == 32 ? 2u : 1u));
+    const uint32_t spread = std::max(1u, (M + slots - 1) / slots);
+    return run_of(M, std::min(std::max(t.units_per_run, 1u), spread));
+}
+
 // Work items: per stream, waves * pairs_per_wave consecutive pairs each; streams
 // in decreasing size so the longest work starts first.
 void build_items(BatchData &b) {
@@ -74,8 +85,8 @@ void build_items(BatchData &b) {
         if (pl.single_symbol) {
             b.items.push_back({s, 0, 1, 1});
         } else {
-            const uint32_t run = run_of(pl.blob->splits(), b.tuning.units_per_run);
-            const uint32_t pairs = pairs_of(pl, b.tuning.units_per_run);
+            const uint32_t run = stream_run(pl, b.tuning);
+            const uint32_t pairs = pairs_of(pl, run);
             for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), run});
         }
         b.cls_count[c] += (uint32_t)(b.items.size() - before);
@@ -381,7 +392,7 @@ recoil_status recoil_autotune(recoil_batch *batch, void *d_ws, void *d_out, uint
         return fail(RECOIL_ERR_HIP, "autotune: event creation failed");
     recoil_tuning best{};
     float best_t = 1e30f;
-    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, p_opts[] = {1, 2, 4, 8}, r_opts[] = {1, 2, 4};
+    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, p_opts[] = {1, 2, 4, 8}, r_opts[] = {1, 2, 4, 8};
     for (uint32_t w : waves_opts)
         for (uint32_t k : k_opts)
             for (uint32_t pp : p_opts)
