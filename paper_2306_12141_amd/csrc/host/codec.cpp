@@ -491,7 +491,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     std::memcpy(p, b.table_bits.data(), b.table_bits.size());
     p += b.table_bits.size();
     for (uint32_t x : b.final_states) { for (int k = 0; k < 4; ++k) *p++ = (uint8_t)(x >> (8 * k)); }
-    std::memcpy(p, b.meta_bits.data(), b.meta_bits.size());
+    if (!b.meta_bits.empty()) std::memcpy(p, b.meta_bits.data(), b.meta_bits.size());
     p += b.meta_bits.size();
     for (uint16_t w : *b.words_buf) { *p++ = (uint8_t)w; *p++ = (uint8_t)(w >> 8); }
     return RECOIL_OK;
@@ -519,7 +519,10 @@ recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
     if (M < 1) return fail(RECOIL_ERR_CORRUPT, "container: zero splits");
     if (B > len / 2 || tbytes > len || mbytes > len) return fail(RECOIL_ERR_CORRUPT, "container: section sizes exceed length");
     if (48 + tbytes + 4ull * W + mbytes + 2 * B != len) return fail(RECOIL_ERR_CORRUPT, "container: length mismatch");
-    if (b->n_symbols / W + 1 < M) return fail(RECOIL_ERR_CORRUPT, "container: more splits than symbol groups");
+    // Every split point carries W 16-bit states, so the metadata size bounds M (and
+    // what is allocated below). Split points may share a symbol group: a stream
+    // cut finer than its groups has more units than groups, some of them empty.
+    if ((M - 1) * 2ull * W > mbytes) return fail(RECOIL_ERR_CORRUPT, "container: more splits than the metadata holds");
     const uint8_t *q = c + 48;
     {
         BitSource s(q, tbytes);

@@ -111,6 +111,27 @@ def test_batch_one_table_class(rc, mixed, width):
         _check_all(batch, out, sel)
 
 
+def test_batch_more_units_than_groups(rc):
+    """Streams cut finer than their symbol groups (some units empty) in one batch."""
+    from paper_2306_12141_amd.batch import Batch
+    streams = []
+    for i, (W, N, dt) in enumerate([(32, 200, np.uint8), (32, 1392, np.uint8), (64, 1392, np.uint16),
+                                    (64, 5000, np.uint8)]):
+        A = 256 if dt == np.uint8 else 4096
+        s = synth.draw_symbols(synth.zipf_pmf(A, 1.1), 900 + i, N, dt)
+        blob = rc.encode(s, lanes=W, quant_bits=12, splits=400, alphabet=A)
+        assert blob.info.splits > -(-N // W)
+        streams.append((s, blob))
+    batch = Batch([b for _, b in streams])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    out.fill_(0x5A)
+    batch.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, streams)
+
+
 def test_graph_replays(rc, mixed):
     """The captured graph replays several times, with eager work in between;
     each replay must equal the eager result."""

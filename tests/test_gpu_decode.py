@@ -106,6 +106,21 @@ def test_streams(rc, ci):
     assert np.array_equal(gpu_decode(rc, blob), s)
 
 
+@pytest.mark.parametrize("W,N,dt,k", [(32, 200, np.uint8, 1), (32, 1392, np.uint8, 1), (32, 1392, np.uint8, 3),
+                                      (64, 1392, np.uint16, 1), (64, 5000, np.uint8, 1), (64, 5000, np.uint8, 4)])
+def test_more_units_than_groups(rc, W, N, dt, k):
+    """A small stream cut finer than its symbol groups (several split points in one
+    group, some units empty), decoded from the encoder's blob and from its container."""
+    A = 256 if dt == np.uint8 else 4096
+    _say("case more units than groups", W, N, np.dtype(dt).name, k)
+    s = _syms(77 + W + N, N, A, dt, 1.1)
+    blob = rc.encode(s, lanes=W, quant_bits=12, splits=400, alphabet=A)
+    assert blob.info.splits > -(-N // W)
+    tuning = dict(chunk_groups=8 if dt == np.uint8 else 4, units_per_run=k)
+    assert np.array_equal(gpu_decode(rc, blob, **tuning), s)
+    assert np.array_equal(gpu_decode(rc, rc.Blob.from_bytes(blob.to_bytes()), **tuning), s)
+
+
 RUN_CASES = [
     # (lanes, n, symbol dtype, alphabet, N, splits, zipf exponent or None)
     (32, 11, np.uint8, 256, 200_003, 29, 1.1),

@@ -85,6 +85,25 @@ def test_deserialize_roundtrip(rc):
     assert rc.Blob.from_bytes(data).to_bytes() == data
 
 
+@pytest.mark.parametrize("W,N,dt", [(32, 200, np.uint8), (32, 1392, np.uint8), (64, 1392, np.uint16),
+                                    (64, 5000, np.uint8), (59, 1392, np.uint16)])
+def test_more_units_than_groups(rc, orc, W, N, dt):
+    """A small stream asked for many splits is cut finer than its symbol groups
+    (several split points in one group, some units empty). The container round-trips,
+    equals the oracle's bytes, and the oracle decodes it back to the input."""
+    A = 256 if dt == np.uint8 else 4096
+    s = _syms(77 + W + N, N, A, dt, 1.1)
+    blob = rc.encode(s, lanes=W, quant_bits=12, splits=400, alphabet=A)
+    G = -(-N // W)
+    assert blob.info.splits > G
+    data = blob.to_bytes()
+    assert data == orc.encode(s, orc.params(lanes=W, quant_bits=12, symbol_bytes=dt().itemsize, alphabet=A),
+                              400).container()
+    assert rc.Blob.from_bytes(data).to_bytes() == data
+    assert np.array_equal(orc.Decoder(data).all(), s)
+    assert np.array_equal(orc.Decoder(blob.combine(G // 2 + 1).to_bytes()).all(), s)
+
+
 def test_corruption_rejected(rc):
     s = _syms(2, 50_000, 256, np.uint8, 1.1)
     data = bytearray(rc.encode(s, lanes=32, quant_bits=11, splits=20).to_bytes())
