@@ -130,6 +130,46 @@ def test_corruption_rejected(rc):
     assert rejected > 0
 
 
+def test_mutated_containers(rc):
+    """Seeded random mutations (bit flips, overwritten runs, truncation) of several
+    containers: the validator either rejects one or accepts a canonical container
+    (it re-serialises to the same bytes); planning and combining it either succeed or
+    return an error status."""
+    rng = np.random.default_rng(31)
+    blobs = [rc.encode(_syms(40 + i, N, A, dt, 1.1), lanes=W, quant_bits=n, splits=M, alphabet=A).to_bytes()
+             for i, (W, n, dt, A, N, M) in enumerate([(32, 11, np.uint8, 256, 20_000, 12),
+                                                       (64, 12, np.uint16, 4096, 9_000, 7),
+                                                       (32, 12, np.uint8, 256, 1_392, 400)])]
+    accepted = rejected = 0
+    for data in blobs:
+        for _ in range(150):
+            d = bytearray(data)
+            kind = rng.integers(4)
+            if kind == 0:
+                for p in rng.integers(len(d), size=rng.integers(1, 9)):
+                    d[p] ^= 1 << int(rng.integers(8))
+            elif kind == 1:
+                d = d[:rng.integers(len(d))]
+            elif kind == 2:
+                p = int(rng.integers(len(d)))
+                d[p:p + 16] = bytes([0xFF if rng.integers(2) else 0]) * len(d[p:p + 16])
+            else:
+                d[int(rng.integers(min(len(d), 256)))] = int(rng.integers(256))
+            try:
+                b = rc.Blob.from_bytes(bytes(d))
+            except rc.RecoilError:
+                rejected += 1
+                continue
+            accepted += 1
+            assert b.to_bytes() == bytes(d)
+            for step in (lambda: rc.Plan(b), lambda: b.combine(3)):
+                try:
+                    step()
+                except rc.RecoilError:   # e.g. a header naming a stream too large to plan
+                    pass
+    assert accepted > 0 and rejected > 0
+
+
 def test_invalid_arguments(rc):
     with pytest.raises(rc.RecoilError):
         rc.encode(np.array([300], dtype=np.uint16), lanes=32, quant_bits=11, alphabet=256)
