@@ -204,6 +204,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     b.total_ws = off;
     b.total_out = std::max<size_t>(out_off, 256);
     build_items(b);
+    if (b.items.size() > b.items_cap) { delete h; return fail(RECOIL_ERR_INVALID_ARG, "batch_create: too many items"); }
     if (workspace_bytes) *workspace_bytes = b.total_ws;
     if (output_bytes) *output_bytes = b.total_out;
     *out = h;
@@ -224,6 +225,7 @@ uint32_t recoil_batch_items(const recoil_batch *batch) { return batch ? (uint32_
 
 static recoil_status upload_items(const recoil::BatchData &b, void *d_ws, hipStream_t stream) {
     using namespace recoil;
+    if (b.items.size() > b.items_cap) return fail(RECOIL_ERR_INVALID_ARG, "batch upload: too many items");
     char *base = static_cast<char *>(d_ws);
     hipError_t e = hipMemcpyAsync(base + b.off_items, b.items.data(), b.items.size() * sizeof(WorkItem),
                                   hipMemcpyHostToDevice, stream);
@@ -261,9 +263,15 @@ recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t 
 recoil_status recoil_batch_set_tuning(recoil_batch *batch, const recoil_tuning *t, void *d_ws, hipStream_t stream) {
     using namespace recoil;
     if (!batch || !t || !tuning_ok(*t)) return fail(RECOIL_ERR_INVALID_ARG, "batch_set_tuning: unsupported tuning");
+    const recoil_tuning old = batch->d.tuning;
     batch->d.tuning = *t;
     build_items(batch->d);
-    if (batch->d.items.size() > batch->d.items_cap) return fail(RECOIL_ERR_INVALID_ARG, "batch_set_tuning: too many items");
+    if (batch->d.items.size() > batch->d.items_cap) {
+        // Keep the batch as it was: its workspace holds items_cap items.
+        batch->d.tuning = old;
+        build_items(batch->d);
+        return fail(RECOIL_ERR_INVALID_ARG, "batch_set_tuning: too many items");
+    }
     if (d_ws) return upload_items(batch->d, d_ws, stream);
     return RECOIL_OK;
 }
