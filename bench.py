@@ -339,6 +339,18 @@ def _time_launches(fn, steps, warmup, torch):
     return sum(per) / len(per), per[len(per) // 2]
 
 
+def _batch_record_bytes(info, tuning):
+    """Per stream of a batched decode: each run's records and table bytes, as in
+    algorithmic_bytes. A stream's run is the tuned length, shortened for a stream
+    too small to give every unit slot of a workgroup a run of that length."""
+    M = max(info.splits, 1)
+    slots = tuning.waves * (2 if info.lanes == 32 else 1)
+    run = max(1, min(max(tuning.units_per_run, 1), -(-M // slots), M))
+    runs = -(-M // run)
+    table = (4 if info.symbol_bytes == 1 else 8) << info.quant_bits
+    return runs * (20 + 4 * info.lanes) + table
+
+
 def run_c3(args, torch, np, rc, synth):
     from paper_2306_12141_amd.batch import Batch
     specs = synth.c3_specs(args.c3_streams)
@@ -377,7 +389,7 @@ def run_c3(args, torch, np, rc, synth):
     per_stream = out_bytes / (p_mean * 1e-3) / 1e9
     log(f"C3: batched {value:.1f} GB/s ({g_mean:.3f} ms), per-stream {per_stream:.1f} GB/s ({p_mean:.3f} ms), "
         f"exact {exact_batched}/{exact_ps}")
-    alg = out_bytes + words_bytes + sum(b.info.splits * (16 + 4 * b.info.lanes) for b in blobs)
+    alg = out_bytes + words_bytes + sum(_batch_record_bytes(b.info, best) for b in blobs)
     achieved = alg / (g_mean * 1e-3) / 1e9
     return {
         "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
