@@ -99,7 +99,10 @@ typedef struct {
 
 /* Launch shape of the decode kernels.
  *   waves          waves per workgroup (8 or 16); the waves of a workgroup share one
- *                  decode table in LDS
+ *                  decode table in LDS. Single-stream decode also takes 1, and 0:
+ *                  16, or 1 when the decode has no more wave-sized pieces of work
+ *                  (runs, or run pairs for W = 32) than the chip has SIMDs, so that
+ *                  they spread over all CUs
  *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
  *                  ring holds 4 K W words (3 K W ring + K W mirror)
  *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)
@@ -197,12 +200,12 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, siz
                                  hipStream_t stream);
 /* Size in bytes of the split metadata as uploaded (part of device_bytes). */
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
-/* Launch shape used by recoil_decode for this plan (default: 16 waves per
- * workgroup; K = 8 groups per super-step for uint8 tables, 4 for uint16;
- * units_per_run 0). pairs_per_wave is ignored.
+/* Launch shape used by recoil_decode for this plan (default: waves 0, i.e. 16
+ * per workgroup or 1 for decodes with few runs; K = 8 groups per super-step for
+ * uint8 tables, 4 for uint16; units_per_run 0). pairs_per_wave is ignored.
  * Errors: INVALID_ARG (unsupported shape). */
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *tuning);
-/* Autotuner for one plan: times every launch shape (waves per workgroup 8/16 x
+/* Autotuner for one plan: times every launch shape (waves per workgroup 1/8/16 x
  * K 4/8 x units per run 0/1/2/4) with recoil_decode on the caller's buffers,
  * `reps` timed launches each after one warm-up, keeps the fastest median and
  * leaves it set on the plan. Results are cached per process, keyed by the

@@ -135,8 +135,27 @@ hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_
     return launch_ss<W, Sym, K, WAVES, 64 / W>(p, t, resident, stream, shape);
 }
 
+constexpr uint32_t kSimdsPerCu = 4;
+
 template <int W, typename Sym>
 hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
+    if (t.waves == 0) {
+        // Automatic: 16 waves per workgroup, or one when the launch has no more
+        // wave-sized pieces of work than the chip has SIMDs. A 16-wave grid would
+        // then put four waves on each SIMD of a few CUs and leave the rest idle,
+        // while each wave's decode is one latency-bound chain that runs faster
+        // with its SIMD to itself.
+        DecodeTuning u = t;
+        u.waves = 16;
+        DecodeShape s{};
+        const hipError_t e = launch_shape<W, Sym>(p, u, stream, &s);
+        if (e != hipSuccess) return e;
+        const uint64_t pieces = s.units_per_wave ? (s.runs + s.units_per_wave - 1) / s.units_per_wave : 0;
+        if (pieces <= (uint64_t)kSimdsPerCu * device_cus()) u.waves = 1;
+        return launch_shape<W, Sym>(p, u, stream, shape);
+    }
+    if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 1) return launch_units<W, Sym, 8, 1>(p, t, stream, shape);
     if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t, stream, shape);
     if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t, stream, shape);
     if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t, stream, shape);

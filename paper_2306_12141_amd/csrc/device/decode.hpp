@@ -44,11 +44,12 @@ struct DecodeParams {
     uint32_t single_symbol;     // nonzero: the stream is one repeated symbol
 };
 
-// Launch shape of the single-stream kernel: waves per workgroup (8 or 16),
-// groups per super-step K (4 or 8), workgroups per CU cap (0 = occupancy
-// limit), units per run (0 = chosen from the number of resident waves).
+// Launch shape of the single-stream kernel: waves per workgroup (1, 8 or 16;
+// 0 = 16, or 1 when the launch has no more waves of work than the chip has
+// SIMDs), groups per super-step K (4 or 8), workgroups per CU cap (0 =
+// occupancy limit), units per run (0 = chosen from the number of resident waves).
 struct DecodeTuning {
-    uint32_t waves = 16, chunk_groups = 4, blocks_per_cu = 0, units_per_run = 0;
+    uint32_t waves = 0, chunk_groups = 4, blocks_per_cu = 0, units_per_run = 0;
 };
 
 // Units per run when the tuning leaves it open: ceil(units / slots), so that

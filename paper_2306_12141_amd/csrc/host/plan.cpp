@@ -32,9 +32,10 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
     pl.blob = bp;
-    // Default launch shape: 16 waves with 8-group super-steps when the table is
-    // small enough for two workgroups per CU (uint8 symbols), 4-group otherwise.
-    pl.tuning.waves = 16;
+    // Default launch shape: waves per workgroup chosen at launch (16, or 1 for
+    // launches with few runs), 8-group super-steps when the table is small enough
+    // for two 16-wave workgroups per CU (uint8 symbols), 4-group otherwise.
+    pl.tuning.waves = 0;
     pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
     pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
@@ -88,7 +89,7 @@ recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, ui
     const uint32_t step = (uint32_t)ceil_div(M, std::min(std::max(target, 1u), M));
     const uint32_t Mc = (M - 1) / step + 1;
     pl.blob = bp;
-    pl.tuning.waves = 16;
+    pl.tuning.waves = 0;
     pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
     pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
@@ -224,7 +225,8 @@ void recoil_plan_free(recoil_plan *plan) { delete plan; }
 recoil_status recoil_plan_set_tuning(recoil_plan *plan, const recoil_tuning *t) {
     using namespace recoil;
     if (!plan || !t) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: bad arguments");
-    const bool ok = (t->waves == 8 || t->waves == 16) && (t->chunk_groups == 4 || t->chunk_groups == 8);
+    const bool ok = (t->waves == 0 || t->waves == 1 || t->waves == 8 || t->waves == 16) &&
+                    (t->chunk_groups == 4 || t->chunk_groups == 8);
     if (!ok) return fail(RECOIL_ERR_INVALID_ARG, "plan_set_tuning: unsupported shape");
     plan->d.tuning.waves = t->waves;
     plan->d.tuning.chunk_groups = t->chunk_groups;
@@ -322,7 +324,7 @@ recoil_status recoil_plan_autotune(recoil_plan *plan, void *d_ws, void *d_out, u
     const DecodeTuning saved = pl.tuning;
     DecodeTuning best = saved;
     float best_t = 1e30f;
-    const uint32_t waves_opts[] = {8, 16}, k_opts[] = {4, 8}, run_opts[] = {0, 1, 2, 4};
+    const uint32_t waves_opts[] = {1, 8, 16}, k_opts[] = {4, 8}, run_opts[] = {0, 1, 2, 4};
     for (uint32_t w : waves_opts)
         for (uint32_t k : k_opts)
             for (uint32_t r : run_opts) {

@@ -158,6 +158,27 @@ def test_units_per_run_shape(rc):
     assert sh.runs <= sh.blocks * sh.waves_per_block           # W = 64: one unit slot per wave
 
 
+@pytest.mark.parametrize("W,splits,dt", [(32, 256, np.uint8), (64, 900, np.uint8), (32, 3000, np.uint16),
+                                          (64, 4096, np.uint8)])
+def test_waves_per_workgroup(rc, W, splits, dt):
+    """The default shape puts one wave in each workgroup when the decode has no more
+    wave-sized pieces of work than the chip has SIMDs, 16 otherwise; explicit 1, 8 and
+    16 waves decode the same symbols."""
+    _say("case waves per workgroup", W, splits, np.dtype(dt).name)
+    A = 256 if dt == np.uint8 else 4096
+    s = _syms(91 + splits, 1 << 20, A, dt, 1.1)
+    blob = rc.encode(s, lanes=W, quant_bits=12, splits=splits, alphabet=A)
+    plan = rc.Plan(blob)
+    sh = plan.shape()
+    pieces = -(-sh.runs // sh.units_per_wave)
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    assert sh.waves_per_block == (1 if pieces <= simds else 16)
+    k = 8 if dt == np.uint8 else 4
+    assert np.array_equal(gpu_decode(rc, blob), s)
+    for w in (1, 8, 16):
+        assert np.array_equal(gpu_decode(rc, blob, waves=w, chunk_groups=k), s)
+
+
 def test_plan_autotune(rc):
     """The single-stream autotuner leaves a valid shape on the plan, the decode with it
     is exact, and a second plan of the same shape is served from the cache."""
@@ -169,7 +190,7 @@ def test_plan_autotune(rc):
     out = plan.allocate_output()
     err = torch.zeros(1, dtype=torch.int32, device="cuda")
     best, ms = plan.autotune(ws, out, err, reps=2)
-    assert best.waves in (8, 16) and best.chunk_groups in (4, 8) and best.units_per_run in (0, 1, 2, 4)
+    assert best.waves in (1, 8, 16) and best.chunk_groups in (4, 8) and best.units_per_run in (0, 1, 2, 4)
     assert ms > 0
     out.fill_(0x3C)
     err.zero_()
