@@ -101,8 +101,9 @@ typedef struct {
  *   waves          waves per workgroup (8 or 16); the waves of a workgroup share one
  *                  decode table in LDS. Single-stream decode also takes 1, and 0:
  *                  16, or 1 when the decode has no more wave-sized pieces of work
- *                  (runs, or run pairs for W = 32) than the chip has SIMDs, so that
- *                  they spread over all CUs
+ *                  (runs, or run pairs for W = 32) than the chip has SIMDs, or 8
+ *                  when 16-wave workgroups would not reach every CU, so that the
+ *                  waves spread over all CUs
  *   chunk_groups   K (4 or 8): symbol groups per super-step; each unit's LDS bitstream
  *                  ring holds 4 K W words (3 K W ring + K W mirror)
  *   pairs_per_wave batched decode only: work-item size in unit pairs per wave (1..64)

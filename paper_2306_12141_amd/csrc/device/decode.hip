@@ -140,18 +140,21 @@ constexpr uint32_t kSimdsPerCu = 4;
 template <int W, typename Sym>
 hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     if (t.waves == 0) {
-        // Automatic: 16 waves per workgroup, or one when the launch has no more
-        // wave-sized pieces of work than the chip has SIMDs. A 16-wave grid would
-        // then put four waves on each SIMD of a few CUs and leave the rest idle,
-        // while each wave's decode is one latency-bound chain that runs faster
-        // with its SIMD to itself.
+        // Automatic: 16 waves per workgroup; one when the launch has no more
+        // wave-sized pieces of work than the chip has SIMDs, and 8 when 16-wave
+        // workgroups would not reach every CU. A 16-wave grid of few pieces puts
+        // four waves on each SIMD of a few CUs and leaves the rest idle, while
+        // each wave's decode is one latency-bound chain that runs faster with
+        // fewer waves beside it.
         DecodeTuning u = t;
         u.waves = 16;
         DecodeShape s{};
         const hipError_t e = launch_shape<W, Sym>(p, u, stream, &s);
         if (e != hipSuccess) return e;
         const uint64_t pieces = s.units_per_wave ? (s.runs + s.units_per_wave - 1) / s.units_per_wave : 0;
-        if (pieces <= (uint64_t)kSimdsPerCu * device_cus()) u.waves = 1;
+        const uint64_t cus = (uint64_t)device_cus();
+        if (pieces <= kSimdsPerCu * cus) u.waves = 1;
+        else if (pieces < 16 * cus) u.waves = 8;
         return launch_shape<W, Sym>(p, u, stream, shape);
     }
     if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1>(p, t, stream, shape);

@@ -46,7 +46,8 @@ struct DecodeParams {
 
 // Launch shape of the single-stream kernel: waves per workgroup (1, 8 or 16;
 // 0 = 16, or 1 when the launch has no more waves of work than the chip has
-// SIMDs), groups per super-step K (4 or 8), workgroups per CU cap (0 =
+// SIMDs, or 8 when 16-wave workgroups would not reach every CU), groups per
+// super-step K (4 or 8), workgroups per CU cap (0 =
 // occupancy limit), units per run (0 = chosen from the number of resident waves).
 struct DecodeTuning {
     uint32_t waves = 0, chunk_groups = 4, blocks_per_cu = 0, units_per_run = 0;

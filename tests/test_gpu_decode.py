@@ -162,8 +162,8 @@ def test_units_per_run_shape(rc):
                                           (64, 4096, np.uint8)])
 def test_waves_per_workgroup(rc, W, splits, dt):
     """The default shape puts one wave in each workgroup when the decode has no more
-    wave-sized pieces of work than the chip has SIMDs, 16 otherwise; explicit 1, 8 and
-    16 waves decode the same symbols."""
+    wave-sized pieces of work than the chip has SIMDs, 8 when 16-wave workgroups would
+    not reach every CU, 16 otherwise; explicit 1, 8 and 16 waves decode the same symbols."""
     _say("case waves per workgroup", W, splits, np.dtype(dt).name)
     A = 256 if dt == np.uint8 else 4096
     s = _syms(91 + splits, 1 << 20, A, dt, 1.1)
@@ -171,8 +171,8 @@ def test_waves_per_workgroup(rc, W, splits, dt):
     plan = rc.Plan(blob)
     sh = plan.shape()
     pieces = -(-sh.runs // sh.units_per_wave)
-    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
-    assert sh.waves_per_block == (1 if pieces <= simds else 16)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert sh.waves_per_block == (1 if pieces <= 4 * cus else 8 if pieces < 16 * cus else 16)
     k = 8 if dt == np.uint8 else 4
     assert np.array_equal(gpu_decode(rc, blob), s)
     for w in (1, 8, 16):
