@@ -137,8 +137,10 @@ class Plan:
     def metadata_device_bytes(self) -> int:
         return _lib.recoil_plan_metadata_device_bytes(self._h)
 
-    def set_tuning(self, waves: int = 16, chunk_groups: int = 4, blocks_per_cu: int = 0,
+    def set_tuning(self, waves: int = 0, chunk_groups: int = 4, blocks_per_cu: int = 0,
                    units_per_run: int = 0) -> None:
+        """waves: 1, 8 or 16 per workgroup, or 0 to choose at launch (16, or fewer
+        when the decode has too few runs to reach every CU)."""
         t = _lib.Tuning(waves, chunk_groups, 1, blocks_per_cu, units_per_run)
         check(_lib.recoil_plan_set_tuning(self._h, C.byref(t)), "recoil_plan_set_tuning")
 

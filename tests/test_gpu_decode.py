@@ -97,13 +97,17 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("waves", [0, 16])
 @pytest.mark.parametrize("ci", range(len(CASES)), ids=[f"W{c[0]}_n{c[1]}_{np.dtype(c[2]).name}_N{c[4]}_M{c[5]}" for c in CASES])
-def test_streams(rc, ci):
+def test_streams(rc, ci, waves):
+    """Each stream shape with the default launch shape (one wave per workgroup for
+    these few units) and with 16-wave workgroups."""
     W, n, dt, A, N, M, z = CASES[ci]
-    _say("case", CASES[ci])
+    _say("case", CASES[ci], waves)
     s = _syms(1000 + ci, N, A, dt, z)
     blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
-    assert np.array_equal(gpu_decode(rc, blob), s)
+    tuning = dict(waves=16, chunk_groups=8 if dt == np.uint8 else 4) if waves else {}
+    assert np.array_equal(gpu_decode(rc, blob, **tuning), s)
 
 
 @pytest.mark.parametrize("W,N,dt,k", [(32, 200, np.uint8, 1), (32, 1392, np.uint8, 1), (32, 1392, np.uint8, 3),
@@ -139,7 +143,7 @@ def test_units_per_run(rc, ci, k):
     _say("case runs", RUN_CASES[ci], k)
     s = _syms(2000 + ci, N, A, dt, z)
     blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
-    assert np.array_equal(gpu_decode(rc, blob, chunk_groups=8 if dt == np.uint8 else 4, units_per_run=k), s)
+    assert np.array_equal(gpu_decode(rc, blob, waves=16, chunk_groups=8 if dt == np.uint8 else 4, units_per_run=k), s)
 
 
 def test_units_per_run_shape(rc):
