@@ -122,6 +122,7 @@ typedef struct {
 } recoil_tuning;
 
 /* Grid of a single-stream decode and the runs it decodes (recoil_plan_shape).
+ * waves_per_block: 1, 8 or 16 (the tuning's, or the one chosen at launch).
  * units_per_wave: runs decoded side by side in one wave: 1 for W = 64; for W = 32,
  * 2 (one per half-wave), or 1 when every run has a wave of its own. */
 typedef struct {
