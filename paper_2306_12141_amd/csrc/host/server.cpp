@@ -325,6 +325,26 @@ std::vector<RequestPtr> admit_locked(recoil_server *s, Slot &sl, bool idle, bool
         }
         return take;
     }
+    // A launch whose pairs would not fill its resident workgroups (the usual case
+    // below full load) cuts its requests into smaller items, about one per
+    // workgroup, so that each request spreads over many CUs instead of a few:
+    // a request's latency is then its own decode time.
+    {
+        uint64_t pairs = 0;
+        uint32_t lut = 16;
+        for (const RequestPtr &r : take) {
+            pairs += r->pairs;
+            lut = std::max(lut, r->content.lut_bytes);
+        }
+        const uint64_t wgs = (uint64_t)std::max(batch_blocks_per_cu(s->tuning, lut), 0) * (uint64_t)device_cus();
+        if (wgs > 0 && pairs < wgs * base_per_item) {
+            const uint32_t fine = (uint32_t)std::max<uint64_t>(1, (pairs + wgs - 1) / wgs);
+            uint64_t n = 0;
+            for (const RequestPtr &r : take) n += items_of(*r, std::min(r->per_item, fine));
+            if (n <= s->cfg.items_per_launch)
+                for (RequestPtr &r : take) r->per_item = std::min(r->per_item, fine);
+        }
+    }
     sl.meta_bytes = meta;
     sl.holds_long = false;
     const uint64_t t = clock_ns();
