@@ -20,10 +20,10 @@ namespace {
 
 using namespace dev;
 
-template <int W, typename Sym, int K>
+template <int W, typename Sym, int K, int SS = 64 / W>
 __device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ring0,
                                 uint32_t lane, uint32_t wave, uint32_t waves, uint32_t first, uint32_t count) {
-    PairDecoder<W, Sym, K> d(p, lut, ring0, lane);
+    PairDecoder<W, Sym, K, SS> d(p, lut, ring0, lane);
     const uint32_t share = wave < count ? (count - 1 - wave) / waves + 1 : 0u;
     uint32_t left = share;
     for (uint32_t q = first + wave; q < first + count; q += waves) d.run(q, --left, share);
@@ -63,7 +63,9 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         p.err = bp.err + wi.stream * bp.err_stride;
         p.n_symbols = d.n_symbols;
         p.units = d.units;
-        p.run = wi.run > 1 ? wi.run : 1u;
+        const bool single = (wi.run & kItemSingle) != 0;
+        const uint32_t run = wi.run & ~kItemSingle;
+        p.run = run > 1 ? run : 1u;
         p.runs = (d.units + p.run - 1) / p.run;
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
@@ -74,8 +76,16 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
                 else static_cast<uint16_t *>(p.out)[i] = (uint16_t)d.fill_symbol;
             }
         } else if (d.lanes == 32) {
-            if (d.symbol_bytes == 1) run_item<32, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
-            else run_item<32, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            if (single) {
+                if (lane < 32) {   // one unit per wave: the upper half-wave idles until the item ends
+                    if (d.symbol_bytes == 1) run_item<32, uint8_t, K, 1>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                    else run_item<32, uint16_t, K, 1>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                }
+            } else if (d.symbol_bytes == 1) {
+                run_item<32, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            } else {
+                run_item<32, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            }
         } else {
             if (d.symbol_bytes == 1) run_item<64, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
             else run_item<64, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);

@@ -23,13 +23,16 @@ static_assert(sizeof(StreamDesc) == 64, "StreamDesc is 64 bytes");
 
 // Consecutive pairs of one stream, decoded by one workgroup. The stream's
 // units are decoded in runs of `run` consecutive units (Sec. 3.3; 0 or 1: every
-// split point), and a pair is two runs (W = 32) or one (W = 64).
+// split point), and a pair is two runs (W = 32) or one (W = 64, or W = 32 with
+// kItemSingle set in `run`: one unit per wave, the upper half-wave idle, for a
+// stream with no more runs than a workgroup has waves).
 struct WorkItem {
     uint32_t stream;
     uint32_t first;     // first pair
     uint32_t count;
-    uint32_t run;       // units per run
+    uint32_t run;       // units per run, | kItemSingle
 };
+constexpr uint32_t kItemSingle = 0x80000000u;
 
 struct BatchParams {
     const unsigned char *ws;      // workspace base

@@ -86,8 +86,13 @@ void build_items(BatchData &b) {
             b.items.push_back({s, 0, 1, 1});
         } else {
             const uint32_t run = stream_run(pl, b.tuning);
-            const uint32_t pairs = pairs_of(pl, run);
-            for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), run});
+            // A W = 32 stream with no more runs than a workgroup has waves decodes one
+            // unit per wave (each run a wave of its own, not half of one).
+            const uint32_t M = pl.blob->splits(), runs = (M + run - 1) / run;
+            const bool single = pl.blob->lanes == 32 && runs <= b.tuning.waves;
+            const uint32_t pairs = single ? runs : pairs_of(pl, run);
+            const uint32_t tag = run | (single ? kItemSingle : 0u);
+            for (uint32_t f = 0; f < pairs; f += per_item) b.items.push_back({s, f, std::min(per_item, pairs - f), tag});
         }
         b.cls_count[c] += (uint32_t)(b.items.size() - before);
     }

@@ -95,10 +95,12 @@ struct Request {
     Content content;
     uint32_t splits_asked = 0;
     uint64_t long_unit_bytes = 0;
+    uint32_t single_max = 0;     // W = 32 requests of at most this many units decode one unit per wave
     PlanData plan;               // unit and lane records of the combined metadata
     uint64_t unit_bytes = 0;     // device bytes of the unit records (aligned)
     uint64_t meta_bytes = 0;     // unit + lane records (aligned)
-    uint32_t pairs = 0;          // unit pairs (W = 32) or units (W = 64)
+    uint32_t pairs = 0;          // unit pairs (W = 32) or units (W = 64, or W = 32 one unit per wave)
+    bool single = false;         // W = 32, one unit per wave
     uint32_t per_item = 0;       // pairs per work item in its launch
     uint32_t items = 0;          // work items in its launch
     bool is_long = false;        // many output bytes per decode unit (serial for long)
@@ -192,7 +194,8 @@ void prepare(Request &r) {
     r.c.out_bytes = full->n_symbols * full->symbol_bytes;
     r.unit_bytes = ws_align(Mc * sizeof(UnitMeta));
     r.meta_bytes = r.unit_bytes + ws_align((uint64_t)Mc * full->lanes * 4);
-    r.pairs = full->lanes == 32 ? (Mc + 1) / 2 : Mc;
+    r.single = full->lanes == 32 && Mc <= r.single_max;
+    r.pairs = full->lanes == 32 && !r.single ? (Mc + 1) / 2 : Mc;
     r.is_long = r.c.out_bytes > r.long_unit_bytes * (uint64_t)Mc;
     r.ready.store(1, std::memory_order_release);
 }
@@ -426,7 +429,8 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
         if (r.items == 0) continue;
         if (r.content.single_symbol) { items[it++] = WorkItem{i, 0, 1, 0}; continue; }
         for (uint64_t f = 0; f < r.pairs; f += r.per_item)
-            items[it++] = WorkItem{i, (uint32_t)f, (uint32_t)std::min<uint64_t>(r.per_item, r.pairs - f), 0};
+            items[it++] = WorkItem{i, (uint32_t)f, (uint32_t)std::min<uint64_t>(r.per_item, r.pairs - f),
+                                   r.single ? kItemSingle : 0u};
     }
     unsigned char *a = s->arena;
     hipError_t e = hipMemcpyAsync(a + sl.ctrl_off, ctrl, ctrl_used, hipMemcpyHostToDevice, sl.stream);
@@ -629,6 +633,7 @@ recoil_status recoil_server_submit(recoil_server *s, uint32_t content, uint32_t 
         r->content = s->contents[content];
         r->splits_asked = splits;
         r->long_unit_bytes = s->cfg.long_unit_bytes;
+        r->single_max = s->cfg.tuning.waves;
         r->c.request_id = s->next_id++;
         r->c.tag = tag;
         r->c.content = content;
