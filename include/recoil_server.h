@@ -9,6 +9,12 @@
  * across up to `hip_streams` launches in flight). Completion is observed through
  * a HIP event per launch.
  *
+ * Work items: a request is cut into items of tuning.waves x pairs_per_wave unit
+ * pairs, or smaller ones (about one per resident workgroup) when the launch's
+ * pairs would not fill the resident workgroups, so that a lightly loaded launch
+ * spreads each request over many CUs. A W = 32 request of at most tuning.waves
+ * units decodes one unit per wave.
+ *
  * Memory: the caller owns one device arena. Its first `resident_bytes` hold the
  * content (bitstream words and decode tables, copied by
  * recoil_server_add_content); the server keeps a small control region per launch
