@@ -82,7 +82,7 @@ enum {
 
 typedef struct {
     uint32_t lanes;         /* W: 32 or 64 for GPU decoding (1..64 accepted by the encoder) */
-    uint32_t quant_bits;    /* n: 1..16 accepted by the encoder; GPU decoding needs n <= 12 */
+    uint32_t quant_bits;    /* n: 1..16 accepted by the encoder; GPU decoding needs 8 <= n <= 12 */
     uint32_t symbol_bytes;  /* 1 (uint8) or 2 (uint16) */
     uint32_t alphabet;      /* A: symbols lie in [0, A); A <= 256 for uint8, <= 65536 for uint16 */
 } recoil_config;
@@ -191,7 +191,7 @@ void recoil_blob_free(recoil_blob *blob);
  * device-friendly layout and reports the device workspace it needs. The plan
  * keeps its own reference to the blob's data; the blob may be freed first.
  * device_bytes: receives the workspace size (bytes, 256-byte aligned sections).
- * Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n > 12, N or B >= 2^32).
+ * Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n outside 8..12, N or B >= 2^32).
  */
 recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, size_t *device_bytes);
 /* Copy bitstream, decode table and unpacked metadata into the caller-owned

@@ -23,7 +23,7 @@ typedef struct recoil_graph recoil_graph;
 recoil_tuning recoil_default_tuning(void);
 
 /*
- * Plan a batch of `count` blobs (each W = 32 or 64, n <= 12). Reports the device
+ * Plan a batch of `count` blobs (each W = 32 or 64, 8 <= n <= 12). Reports the device
  * workspace size (words, tables, unit records, stream descriptors, work items,
  * queue counter) and the output size: stream i's symbols land at the offset given
  * by recoil_batch_output_offset (256-byte aligned). tuning: NULL for the default.

@@ -27,7 +27,8 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     const BlobData &b = *bp;
     const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
-    if (n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs n <= 12");
+    // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
+    if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
     if (b.n_symbols >= (1ull << 32) || b.n_words() + kChunkPadWords >= (1ull << 31))
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
@@ -83,7 +84,8 @@ recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, ui
     const BlobData &b = *bp;
     const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
-    if (n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs n <= 12");
+    // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
+    if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
     if (b.n_symbols >= (1ull << 32) || b.n_words() + kChunkPadWords >= (1ull << 31))
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
     const uint32_t step = (uint32_t)ceil_div(M, std::min(std::max(target, 1u), M));

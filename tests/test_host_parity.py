@@ -185,5 +185,9 @@ def test_plan_rejects_unsupported(rc):
         rc.Plan(rc.encode(s, lanes=16, quant_bits=11, splits=4))
     with pytest.raises(rc.RecoilError):
         rc.Plan(rc.encode(s, lanes=32, quant_bits=13, splits=4))
+    # Eq. 2 on the GPU multiplies f by x >> n in 24 bits, which holds only for n >= 8.
+    with pytest.raises(rc.RecoilError) as e:
+        rc.Plan(rc.encode(s % 64, lanes=32, quant_bits=7, splits=4, alphabet=64))
+    assert e.value.status == -4
     plan = rc.Plan(rc.encode(s, lanes=32, quant_bits=11, splits=4))
     assert plan.device_bytes > 0 and plan.splits == 4

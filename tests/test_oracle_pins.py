@@ -94,6 +94,31 @@ def test_quantize_properties(orc):
         orc.quantize(np.ones(9, dtype=np.uint64), 3)       # 9 symbols > 2^3 slots
 
 
+@pytest.mark.parametrize("counts,n,expect", [
+    # Shortfall, equal remainders: 3 x floor(8/3) = 6 < 8; the two missing units go to
+    # the smaller symbols first (a larger-symbol-first rule would give [2, 3, 3]).
+    ([1, 1, 1], 3, [3, 3, 2]),
+    # Shortfall ordered by remainder, not by count: 16 c / 10 = 8 r0, 4 r8, 3 r2; the
+    # one missing unit goes to the largest remainder, symbol 1 (by count it would be [9, 4, 3]).
+    ([5, 3, 2], 4, [8, 5, 3]),
+    # Excess, tie on the largest f: 8 c / 23 = 3, 3 and three rare symbols raised to 1 sum
+    # to 9; the one unit comes off the smaller symbol (larger-symbol-first: [3, 2, 1, 1, 1]).
+    ([10, 10, 1, 1, 1], 3, [2, 3, 1, 1, 1]),
+    # Excess taken from the largest f, not the smallest f > 1: 8 c / 33 = 4, 2, 0 -> 1 x 3
+    # sums to 9 (smallest-first would give [4, 1, 1, 1, 1]).
+    ([20, 10, 1, 1, 1], 3, [3, 2, 1, 1, 1]),
+    # Excess of two over a tie: 8 c / 24 = 3, 3, then 1 x 4 = 10; the first unit comes off
+    # symbol 0, which leaves symbol 1 the unique largest for the second.
+    ([10, 10, 1, 1, 1, 1], 3, [2, 2, 1, 1, 1, 1]),
+])
+def test_quantize_tie_breaks(orc, counts, n, expect):
+    """The quantisation rule, worked by hand: f = max(1, floor(c 2^n / N)); a shortfall
+    is handed out by largest remainder c 2^n mod N (ties: smaller symbol); an excess is
+    removed one unit at a time from the largest f > 1 (ties: smaller symbol)."""
+    f = orc.quantize(np.array(counts, dtype=np.uint64), n)
+    assert f.tolist() == expect
+
+
 # ---------------------------------------------------------------------------
 # The paper's worked example (Sec. 4.1, Tables 1-2, Sec. 4.3)
 # ---------------------------------------------------------------------------
@@ -267,6 +292,28 @@ def test_heuristic_hand_worked(orc, lanes, N, units, expect):
     assert np.array_equal(orc.Decoder(enc.container()).all(), s)
 
 
+def test_heuristic_recomputes_target(orc):
+    """Def. 4.1 with T taken from the symbols that remain (reading 7), worked by hand
+    on the W = 1 closed-form stream, where word w has Imax = Imin = 2w and t_s = 1.
+
+    N = 13, three units. Split 1: T = ceil(13 / 3) = 5, t = 2w + 1,
+    H = |2w - 4| + |2w - 5| is 1 at w = 2 (Imax 4). Split 2: T = ceil((13 - 5) / 2) = 4,
+    t = 2w - 4, H = |2w - 8| + |2w - 9| is 1 at w = 4 (Imax 8): units of 5, 4 and 4
+    symbols. A fixed T = 5 would give H = |2w - 9| + |2w - 10|, smallest at w = 5
+    (Imax 10), and units of 5, 6 and 2 symbols.
+    """
+    N = 13
+    s = _rng_symbols(1313, N, 256)
+    p = orc.params(lanes=1, quant_bits=8, alphabet=256)
+    enc = orc.encode(s, p, 3, freq=np.ones(256, dtype=np.uint32))
+    assert enc.threads == 3
+    got = [(enc.split(k).pos, enc.split(k).imax) for k in (1, 2)]
+    assert got == [(2, 4), (4, 8)]
+    dec = orc.Decoder(enc.container())
+    assert [dec.thread_range(t) for t in (1, 2, 3)] == [(0, 4), (4, 8), (8, 13)]
+    assert np.array_equal(dec.all(), s)
+
+
 def test_heuristic_properties(orc, c0):
     spec, s, p, enc, c = c0
     dec = orc.Decoder(c)
@@ -309,6 +356,24 @@ def test_combine(orc, c0, target):
     info0, info1 = orc.info(c), orc.info(cc)
     assert info1.n_words == info0.n_words                # the bitstream is untouched
     assert _fmt.parse(cc)["words"].tobytes() == _fmt.parse(c)["words"].tobytes()
+
+
+@pytest.mark.parametrize("target,step,kept", [
+    (100, 3, list(range(3, 256, 3))),          # 85 split points 3, 6, ..., 255: 86 units
+    (7, 37, [37, 74, 111, 148, 185, 222]),     # 259 > 255 is not a split point: 7 units
+    (128, 2, list(range(2, 256, 2))),
+])
+def test_combine_keeps_every_step_th(orc, c0, target, step, kept):
+    """Sec. 3.3 / reading 10: combining M_in = 256 units to `target` keeps exactly the
+    split points whose 1-based number is a multiple of step = ceil(256 / target)."""
+    spec, s, p, enc, c = c0
+    assert spec.splits == 256 and -(-256 // target) == step
+    d1 = orc.Decoder(orc.combine(c, target))
+    assert d1.threads == len(kept) + 1
+    # Thread t of the combined stream ends at the Imin of its kept split point t.
+    ends = [d1.thread_range(t)[1] for t in range(1, d1.threads)]
+    assert ends == [enc.split(k).imin for k in kept]
+    assert d1.thread_range(d1.threads)[1] == len(s)
 
 
 # ---------------------------------------------------------------------------
