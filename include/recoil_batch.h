@@ -54,6 +54,23 @@ recoil_status recoil_batch_get_tuning(const recoil_batch *batch, recoil_tuning *
 recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_workspace, void *d_out, uint32_t *d_error,
                                   hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): recoil_decode_batch with
+ * the queue heads in a statically allocated device array of the library instead
+ * of the workspace, so d_workspace is only read. The array is 256 bytes per GPU
+ * (one head per table class, 128 bytes apart), held by every GPU the library runs
+ * on until the process ends; each launch's head is reset by a kernel, not a
+ * memset. The first call on a device looks up the array's address on that device
+ * (hipGetSymbolAddress, current device), so make it outside graph capture. Calls
+ * that overlap on one GPU share the heads and race: serialise them (one stream, or
+ * events). Allocates nothing, synchronises nothing. Arguments and output as
+ * recoil_decode_batch. Errors: INVALID_ARG, UNSUPPORTED (more table classes than
+ * heads; not produced by recoil_batch_create), HIP.
+ */
+recoil_status recoil_decode_batch_noalloc(const recoil_batch *batch, const void *d_workspace, void *d_out,
+                                          uint32_t *d_error, hipStream_t stream);
+
 /* Baseline: the single-stream decoder launched once per stream, in order, on `stream`. */
 recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const void *d_workspace, void *d_out,
                                              uint32_t *d_error, hipStream_t stream);

@@ -96,6 +96,7 @@ recoil_batch_upload = _sig("recoil_batch_upload", [P, P, sz, P])
 recoil_batch_set_tuning = _sig("recoil_batch_set_tuning", [P, C.POINTER(Tuning), P, P])
 recoil_batch_get_tuning = _sig("recoil_batch_get_tuning", [P, C.POINTER(Tuning)])
 recoil_decode_batch = _sig("recoil_decode_batch", [P, P, P, P, P])
+recoil_decode_batch_noalloc = _sig("recoil_decode_batch_noalloc", [P, P, P, P, P])
 recoil_decode_batch_per_stream = _sig("recoil_decode_batch_per_stream", [P, P, P, P, P])
 recoil_batch_graph_create = _sig("recoil_batch_graph_create", [P, P, P, P, C.POINTER(P)])
 recoil_graph_launch = _sig("recoil_graph_launch", [P, P])

@@ -79,6 +79,12 @@ class Batch:
         check(_lib.recoil_decode_batch(self._h, C.c_void_p(ws.data_ptr()), C.c_void_p(out.data_ptr()),
                                        C.c_void_p(err.data_ptr()), _stream_handle(stream)), "recoil_decode_batch")
 
+    def decode_noalloc(self, ws, out, err, stream=None):
+        """recoil_decode_batch_noalloc: queue heads in the library's static device array."""
+        check(_lib.recoil_decode_batch_noalloc(self._h, C.c_void_p(ws.data_ptr()), C.c_void_p(out.data_ptr()),
+                                               C.c_void_p(err.data_ptr()), _stream_handle(stream)),
+              "recoil_decode_batch_noalloc")
+
     def decode_per_stream(self, ws, out, err, stream=None):
         check(_lib.recoil_decode_batch_per_stream(self._h, C.c_void_p(ws.data_ptr()), C.c_void_p(out.data_ptr()),
                                                   C.c_void_p(err.data_ptr()), _stream_handle(stream)),

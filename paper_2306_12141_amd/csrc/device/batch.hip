@@ -10,11 +10,16 @@
 // a one-thread kernel launched just before, so the pair of launches can be
 // captured in a HIP graph and replayed.
 #include <algorithm>
+#include <mutex>
 
 #include "batch.hpp"
 #include "decode_core.hpp"
 
 namespace recoil {
+
+// Queue heads of recoil_decode_batch_noalloc: one per table class, kStaticHeadStride
+// words apart (one 128-byte line each). Every decode on a device shares its copy.
+static __device__ __align__(256) uint32_t scratch[kStaticScratchWords];
 
 namespace {
 
@@ -139,7 +144,30 @@ hipError_t launch(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t str
     return hipGetLastError();
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices];
+
 }  // namespace
+
+hipError_t static_scratch(uint32_t **ptr) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // The array's device address on this device; the host-side name is only a stand-in.
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t stream) {
     if (bp.n_items == 0) return hipSuccess;

@@ -58,6 +58,12 @@ struct BatchTuning {
     uint32_t blocks_per_cu;// 0: occupancy limit
 };
 
+// Statically allocated queue heads (recoil_decode_batch_noalloc): one device
+// array per GPU of kStaticScratchWords words, a head every kStaticHeadStride words.
+constexpr uint32_t kStaticScratchWords = 64, kStaticHeadStride = 32;
+// Device address of that array on the current device, looked up once per device.
+hipError_t static_scratch(uint32_t **ptr);
+
 // Persistent batched launch: queue-head reset kernel + decode kernel on `stream`.
 hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t stream);
 // Occupancy-derived workgroups per CU for a tuning (0 if the tuning is not available).

@@ -297,6 +297,32 @@ recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_ws, void *d
     return RECOIL_OK;
 }
 
+recoil_status recoil_decode_batch_noalloc(const recoil_batch *batch, const void *d_ws, void *d_out, uint32_t *d_error,
+                                         hipStream_t stream) {
+    using namespace recoil;
+    if (!batch || !d_ws || !d_out || !d_error) return fail(RECOIL_ERR_INVALID_ARG, "decode_batch_noalloc: bad arguments");
+    const BatchData &b = batch->d;
+    // One queue head per table class in the library's static device array.
+    static_assert(kBatchClasses * kStaticHeadStride <= kStaticScratchWords, "static queue heads do not fit");
+    uint32_t classes = 0;
+    for (uint32_t c = 0; c < kBatchClasses; ++c) classes += b.cls_count[c] ? 1u : 0u;
+    if (classes * kStaticHeadStride > kStaticScratchWords)
+        return fail(RECOIL_ERR_UNSUPPORTED, "decode_batch_noalloc: more table classes than static queue heads");
+    uint32_t *heads = nullptr;
+    hipError_t e = static_scratch(&heads);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch_noalloc: ") + hipGetErrorString(e));
+    // The workspace is only read: params_of's head pointer into it is replaced below.
+    void *ws = const_cast<void *>(d_ws);
+    for (uint32_t c = 0; c < kBatchClasses; ++c) {
+        if (b.cls_count[c] == 0) continue;
+        BatchParams bp = params_of(b, c, ws, d_out, d_error);
+        bp.head = heads + c * kStaticHeadStride;
+        e = launch_batch(bp, device_tuning(b.tuning), stream);
+        if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch_noalloc: ") + hipGetErrorString(e));
+    }
+    return RECOIL_OK;
+}
+
 recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const void *d_ws, void *d_out,
                                              uint32_t *d_error, hipStream_t stream) {
     using namespace recoil;
