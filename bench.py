@@ -1,30 +1,30 @@
 #!/usr/bin/env python3
 """Recoil decode benchmark on one MI355X.
 
-Default workload: a single 256 MiB uint8 stream, iid Zipf(s = 1.1) over a
+Headline (`value`): a single 256 MiB uint8 stream, iid Zipf(s = 1.1) over a
 seeded permutation of 256 symbols, n = 12, W = 64 interleaved lanes (--lanes),
 encoded with 65536 splits. One step is one recoil_decode of the whole stream
 with the bitstream, table and metadata already resident in HBM. `value` is
 decoded output bytes per second (1 GB = 1e9 B) over the timed steps.
 
-Also reported: the same stream at W = 32 (the workload measures both), the
-W = 32 stream combined down to 16384 / 4096 / 1024 / 256 splits (metadata and
-transferred bytes, GB/s), the host-to-device upload time, the dominant
-kernel's roofline position, and the CPU oracle timed on the host cores on a
-bounded sample of the same workload.
+The same line also carries (each bit-exact against the input symbols):
+  extras: the stream at W = 32, every split point used, a decode after evicting
+      the caches, the W = 32 stream combined to 16384 / 4096 / 1024 / 256 splits,
+      the small Laplace stream, and the host-to-device upload;
+  c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8 and uint16,
+      n 10..12, about 8 KiB per split) decoded by one hipGraph replay of the
+      persistent batched kernel (autotuned launch shape) versus one single-stream
+      launch per stream, every stream of both checked;
+  c4: the serving loop, Poisson arrivals at 2000 requests/s over a resident corpus
+      of 64 KiB..64 MiB streams stored with about 1 KiB per split; each request
+      asks for a log-uniform number of decode units (combined at admission);
+      32 GiB request budget; sustained decoded GB/s and p50/p99/p99.9 latency
+      from arrival to observed completion, every request's output compared on
+      the device with its content before release.
+Each carries `roofline` (HBM and ALU ceilings of its dominant kernel) and
+`cpu_baseline` (the CPU oracle on a bounded sample of the same workload).
 
-Other workloads (each prints its own JSON line):
-  --workload c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8
-      and uint16, n 10..12, about 8 KiB per split) decoded by one hipGraph replay
-      of the persistent batched kernel (autotuned launch shape) versus one
-      single-stream launch per stream; value = batched decoded GB/s.
-  --workload c4: serving loop, Poisson arrivals at 2000 requests/s over a resident
-      corpus of 64 KiB..64 MiB streams stored with about 1 KiB per split; each
-      request asks for a log-uniform number of decode units (combined at
-      admission); 32 GiB request budget; value = sustained decoded GB/s, with
-      p50/p99/p99.9 latency from arrival to observed completion.
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c3|c4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c1|c3|c4]
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
 
@@ -41,34 +41,100 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Plain-ALU peak: 256 CUs x 4 SIMDs, one wave64 integer VALU instruction per SIMD
+# every 4 cycles (16 lanes per cycle) at the 2.4 GHz peak engine clock.
+SIMDS = 256 * 4
+CLOCK_GHZ = 2.4
+VALU_PEAK_TLANEOPS = SIMDS * 16 * CLOCK_GHZ / 1e3      # 39.32 T int32 lane-ops/s
 METRIC = "decoded GB/s on 1 MI355X (batched vs per-stream launch, bit-exact); p99 latency"
+
+DEV = "paper_2306_12141_amd/csrc/device/"
+KERNEL_SOURCES = {
+    "decode_units": (DEV + "decode.hip", DEV + "decode.hpp", DEV + "decode_core.hpp"),
+    "decode_batch": (DEV + "batch.hip", DEV + "batch.hpp", DEV + "decode.hpp", DEV + "decode_core.hpp"),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "decode_units") -> str:
     h = hashlib.sha256()
-    for rel in ("paper_2306_12141_amd/csrc/device/decode.hip", "paper_2306_12141_amd/csrc/device/decode.hpp",
-                "paper_2306_12141_amd/csrc/device/decode_core.hpp"):
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this kernel."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def _profile_record(fname: str, key: str, kernel: str):
+    """A committed per-launch record from rocprofv3 counter runs, if it was taken on this kernel source."""
     try:
-        with open(path) as fh:
+        with open(os.path.join(ROOT, "profiles", fname)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     ent = rec.get(key)
-    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+    if not ent or ent.get("kernel_hash") != kernel_source_hash(kernel):
         return None
-    return ent.get("bytes_per_launch")
+    return ent
+
+
+def measured_traffic(key: str, kernel: str = "decode_units"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
+    ent = _profile_record("traffic.json", key, kernel)
+    return ent.get("bytes_per_launch") if ent else None
+
+
+def roofline(key: str, kernel: str, alg_bytes: int, kernel_ms: float, **extra) -> dict:
+    """Position of one kernel against both ceilings that can bind it.
+
+    HBM: algorithmic bytes per launch / mean launch duration against 8 TB/s.
+    ALU: the VALU instructions one launch issues (SQ_INSTS_VALU, from committed
+    counter runs of this kernel source) need count x 4 cycles / (1024 SIMDs x
+    2.4 GHz) at the least; as a rate, count x 64 lanes / duration against
+    39.3 T int32 lane-ops/s. `bound` is the ceiling with the longer floor; the
+    top-level achieved/peak/frac are that ceiling's."""
+    hbm_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    hbm = {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+           "ceiling_ms": round(alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 5)}
+    cnt = _profile_record("counters.json", key, kernel)
+    alu = None
+    if cnt and cnt.get("per_launch", {}).get("SQ_INSTS_VALU"):
+        valu = float(cnt["per_launch"]["SQ_INSTS_VALU"])
+        lane_ops = valu * 64
+        ach = lane_ops / (kernel_ms * 1e-3) / 1e12
+        alu = {"achieved": round(ach, 2), "peak": round(VALU_PEAK_TLANEOPS, 2), "unit": "T int32 lane-ops/s",
+               "frac": round(ach / VALU_PEAK_TLANEOPS, 4),
+               "ceiling_ms": round(valu * 4 / (SIMDS * CLOCK_GHZ * 1e9) * 1e3, 5),
+               "valu_per_launch": int(valu), "salu_per_launch": cnt["per_launch"].get("SQ_INSTS_SALU"),
+               "valu_per_64_symbols": cnt.get("valu_per_64_symbols"),
+               "source": f"profiles/counters.json[{key}]"}
+    top = alu if alu and alu["ceiling_ms"] > hbm["ceiling_ms"] else hbm
+    out = {"bound": "alu" if top is alu else "hbm", "achieved": top["achieved"], "peak": top["peak"],
+           "unit": top["unit"], "frac": top["frac"], "traffic": measured_traffic(key, kernel), "kernel": kernel,
+           "alg_bytes_per_launch": alg_bytes, "kernel_ms_mean": round(kernel_ms, 5), "hbm": hbm, "alu": alu}
+    out.update(extra)
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Host threads the CPU legs use: the CPUs this process may run on, at most 16
+    (one GPU's share of the host on the benchmark machines)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(n, 16))
 
 
 # Untimed decoding before the warm-up steps, in milliseconds. An idle MI355X sits at a
@@ -150,29 +216,66 @@ def check_exact(plan, out, symbols, err, np):
     return ok
 
 
+def _median_time(fn, reps: int = 3):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
 def cpu_oracle_baseline(spec, sample_symbols: int, np):
-    """The oracle, as it stands, on a bounded prefix of the same workload, all host cores."""
+    """The oracle, as it stands, on a bounded prefix of the same stream: (i) serial
+    whole-stream interleaved decode on 1 core, (ii) per-split decode of every unit on 1
+    core (synchronisation included), (iii) the same over all host threads. Median of 3
+    runs each; `value` is (iii)."""
     import oracle
     import synth
-    s = spec.generate()[:sample_symbols] if spec.n_symbols <= sample_symbols else None
-    if s is None:
-        sub = synth.StreamSpec(**{**spec.__dict__, "n_symbols": sample_symbols})
-        s = sub.generate()
-    splits = max(1, int(spec.splits * sample_symbols / spec.n_symbols))
+    sub = synth.StreamSpec(**{**spec.__dict__, "n_symbols": min(sample_symbols, spec.n_symbols)})
+    s = sub.generate()
+    splits = max(1, int(spec.splits * len(s) / spec.n_symbols))
     p = oracle.params(lanes=spec.lanes, quant_bits=spec.quant_bits, symbol_bytes=spec.symbol_bytes,
                       alphabet=spec.alphabet)
-    cont = oracle.encode(s, p, splits).container()
-    dec = oracle.Decoder(cont)
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
-    t0 = time.perf_counter()
-    out = dec.all(aligned=True, workers=cores)
-    dt = time.perf_counter() - t0
-    assert np.array_equal(out, s)
-    return {"value": round(len(s) * spec.symbol_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"first {len(s)} symbols of the workload, encoded by the oracle with {splits} splits; "
-                      f"all {splits} decode units over {cores} std::threads; {dt:.2f} s wall"}
+    dec = oracle.Decoder(oracle.encode(s, p, splits).container())
+    cores = host_cores()
+    nbytes = len(s) * spec.symbol_bytes
+    assert np.array_equal(dec.serial(), s) and np.array_equal(dec.all(aligned=True, workers=cores), s)
+    t_serial = _median_time(lambda: dec.serial())
+    t_one = _median_time(lambda: dec.all(aligned=True, workers=1))
+    t_all = _median_time(lambda: dec.all(aligned=True, workers=cores))
+    gbs = lambda t: round(nbytes / t / 1e9, 4)
+    return {"value": gbs(t_all), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "timings": {"serial_whole_stream_1_core": gbs(t_serial), "per_split_1_core": gbs(t_one),
+                        f"per_split_{cores}_threads": gbs(t_all)},
+            "sample": f"first {len(s)} symbols of the workload ({nbytes / 2**20:.0f} MiB), encoded by the oracle "
+                      f"with {splits} splits (same symbols per split); value = all {splits} decode units over "
+                      f"{cores} std::threads, {t_all:.3f} s (median of 3); 1 core: serial {t_serial:.2f} s, "
+                      f"per-split {t_one:.2f} s"}
+
+
+def cpu_oracle_streams(containers, np, symbols, label: str, budget_s: float = 12.0):
+    """The oracle decoding whole containers one after another, each with all its units
+    spread over the host threads (a unit per thread at a time), until about budget_s
+    of wall time; every output checked."""
+    import oracle
+    cores = host_cores()
+    done, nbytes, t = 0, 0, 0.0
+    for c, s in zip(containers, symbols):
+        dec = oracle.Decoder(c)
+        t0 = time.perf_counter()
+        out = dec.all(aligned=True, workers=min(cores, dec.threads))
+        t += time.perf_counter() - t0
+        assert np.array_equal(out, s), f"{label}: oracle output differs"
+        done += 1
+        nbytes += s.nbytes
+        if t > budget_s:
+            break
+    return {"value": round(nbytes / t / 1e9, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{label}: {done} streams, {nbytes / 2**20:.0f} MiB decoded, each by the oracle's per-split "
+                      f"decoder over min({cores}, its units) std::threads, {t:.2f} s"}
 
 
 def algorithmic_bytes(spec, info, runs):
@@ -231,7 +334,9 @@ def run_c1(args, torch, np, rc, synth):
                   "units_per_run": shape.units_per_run, "runs": shape.runs, "units_per_wave": shape.units_per_wave},
     }
     if not args.no_extras:
-        result["cache_cold"] = time_cold(plan, ws, out, err, torch)
+        cold = time_cold(plan, ws, out, err, torch)
+        cold["hbm_frac"] = round(alg_bytes / (cold["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        result["cache_cold"] = cold
         log(f"W={lanes} after evicting the caches: {result['cache_cold']['median_ms']:.4f} ms")
     if not args.no_extras and shape.units_per_run != 1:
         # The same decode using every split point (one run per unit).
@@ -244,7 +349,7 @@ def run_c1(args, torch, np, rc, synth):
             "decoded_gbs": round(out_bytes / (t1["ms_per_step"] * 1e-3) / 1e9, 2),
             "ms_per_step": round(t1["ms_per_step"], 5), "kernel_ms_mean": round(t1["kernel_ms_mean"], 5),
             "exact": ok1, "runs": one.runs,
-            "roofline_frac": round(algorithmic_bytes(spec, info, one.runs) / (t1["kernel_ms_mean"] * 1e-3) / 1e9
+            "hbm_frac": round(algorithmic_bytes(spec, info, one.runs) / (t1["kernel_ms_mean"] * 1e-3) / 1e9
                                    / HBM_PEAK_GBS, 4)}
         log(f"W={lanes} every split point: {t1['ms_per_step']:.4f} ms/step, exact={ok1}")
         plan.set_tuning(waves=shape.waves_per_block, chunk_groups=kg, units_per_run=shape.units_per_run)
@@ -352,6 +457,8 @@ def _batch_record_bytes(info, tuning):
 
 
 def run_c3(args, torch, np, rc, synth):
+    """Mixed batch: one graph replay of the persistent batched kernel against one
+    single-stream launch per stream, both checked on every stream."""
     from paper_2306_12141_amd.batch import Batch
     specs = synth.c3_specs(args.c3_streams)
     streams = _encode_specs(specs, rc, np, "C3")
@@ -363,57 +470,72 @@ def run_c3(args, torch, np, rc, synth):
     ws, out, err = batch.allocate()
     batch.upload(ws)
     torch.cuda.synchronize()
-    log(f"C3: {batch.items} work items, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
+    n_items = batch.items
+    log(f"C3: {n_items} work items, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
     best, best_ms = batch.autotune(ws, out, err, reps=3)
     shape = {"waves": best.waves, "chunk_groups": best.chunk_groups, "pairs_per_wave": best.pairs_per_wave,
              "units_per_run": best.units_per_run}
     log(f"C3: autotuned {shape} ({best_ms:.3f} ms)")
     graph = batch.graph(ws, out, err)
     stream = torch.cuda.current_stream()
+
+    def all_exact():
+        torch.cuda.synchronize()
+        host = out.cpu().numpy()
+        ok = int(err.item()) == 0
+        bad = 0
+        for i, (s, _) in enumerate(streams):
+            off, n = batch.output_range(i)
+            if not np.array_equal(host[off:off + n].view(s.dtype), s):
+                bad += 1
+        return ok and bad == 0, bad
+
+    out.fill_(0x5A)
     g_mean, g_med = _time_launches(lambda: graph.launch(stream), args.steps, args.warmup, torch)
-    host = out.cpu().numpy()
-    exact_batched = int(err.item()) == 0
-    for i, (s, _) in enumerate(streams):
-        off, n = batch.output_range(i)
-        exact_batched &= bool(np.array_equal(host[off:off + n].view(s.dtype), s))
-    out.fill_(0)
+    exact_batched, bad_b = all_exact()
+    out.fill_(0xA5)
     ps_steps = max(3, args.steps // 4)
     p_mean, p_med = _time_launches(lambda: batch.decode_per_stream(ws, out, err), ps_steps, 1, torch)
-    host = out.cpu().numpy()
-    exact_ps = int(err.item()) == 0
-    for i, (s, _) in enumerate(streams):
-        off, n = batch.output_range(i)
-        exact_ps &= bool(np.array_equal(host[off:off + n].view(s.dtype), s))
-    del host
+    exact_ps, bad_p = all_exact()
     value = out_bytes / (g_mean * 1e-3) / 1e9
     per_stream = out_bytes / (p_mean * 1e-3) / 1e9
     log(f"C3: batched {value:.1f} GB/s ({g_mean:.3f} ms), per-stream {per_stream:.1f} GB/s ({p_mean:.3f} ms), "
-        f"exact {exact_batched}/{exact_ps}")
+        f"exact {exact_batched}/{exact_ps} (streams differing: {bad_b}/{bad_p})")
     alg = out_bytes + words_bytes + sum(_batch_record_bytes(b.info, best) for b in blobs)
-    achieved = alg / (g_mean * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        pick = list(range(0, len(streams), max(1, len(streams) // 64)))
+        cpu = cpu_oracle_streams((blobs[i].to_bytes() for i in pick), np, (streams[i][0] for i in pick),
+                                 f"every {max(1, len(streams) // 64)}th stream of the batch (containers from the "
+                                 f"host encoder, byte-identical to the oracle's)")
+        log(f"C3 cpu oracle: {cpu['value']} GB/s")
+    del ws, out, err, graph, batch
     return {
-        "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(g_mean, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic (seeded mixed streams; the paper's corpora are not available)",
+        "value": round(value, 3), "unit": "GB/s", "ms_per_step": round(g_mean, 5), "steps": args.steps,
+        "warmup": args.warmup, "exact": exact_batched and exact_ps, "dtype": "u32",
         "config": {"workload": f"{len(streams)} mixed streams, 4 KiB-16 MiB log-uniform, Laplace/Zipf/uniform, "
                                f"3/4 uint8 (A=256) 1/4 uint16 (A=4096), n 10-12, W=32, ~8 KiB per split; "
-                               f"one hipGraph replay of the persistent batched kernel",
+                               f"one hipGraph replay of the persistent batched kernel (one launch per table class)",
                    "streams": len(streams), "decoded_bytes": out_bytes, "words_bytes": words_bytes,
-                   "metadata_bytes": meta_bytes, "work_items": batch.items, "tuning": shape,
-                   "bit_exact": exact_batched and exact_ps},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "decode_batch",
-                     "alg_bytes_per_launch": alg, "kernel_ms_mean": round(g_mean, 5)},
-        "cpu_baseline": None,
-        "extras": {"per_stream": {"decoded_gbs": round(per_stream, 3), "ms": round(p_mean, 5),
-                                  "ms_median": round(p_med, 5), "launches": len(streams)},
-                   "batched_ms_median": round(g_med, 5), "speedup_vs_per_stream": round(p_mean / g_mean, 3),
-                   "autotune_best_ms": round(best_ms, 4)},
+                   "metadata_bytes": meta_bytes, "work_items": n_items, "tuning": shape,
+                   "streams_checked": len(streams)},
+        "per_stream": {"value": round(per_stream, 3), "unit": "GB/s", "ms": round(p_mean, 5),
+                       "ms_median": round(p_med, 5), "launches": len(streams), "exact": exact_ps,
+                       "how": "one single-stream recoil_decode launch per stream, in order, on one HIP stream"},
+        "speedup_vs_per_stream": round(p_mean / g_mean, 3),
+        "batched_ms_median": round(g_med, 5), "autotune_best_ms": round(best_ms, 4),
+        "roofline": roofline("decode_batch_c3", "decode_batch", alg, g_mean,
+                             timing="mean over the timed graph replays, HIP events around each replay"),
+        "cpu_baseline": cpu,
     }
 
 
+LATENCY_BUCKETS = ((1, 1), (2, 7), (8, 63), (64, 511), (512, 1 << 40))
+
+
 def run_c4(args, torch, np, rc, synth):
+    """Serving loop at the configured Poisson load; every completed request's output is
+    compared on the device with its content before the request is released."""
     import threading
     from paper_2306_12141_amd.server import Server, now_ns
     specs = synth.c4_corpus_specs(args.c4_corpus)
@@ -425,6 +547,7 @@ def run_c4(args, torch, np, rc, synth):
     ctrl = ((256 + 2 * ((max_batch * 4 + 255) // 256 * 256) + (max_batch * 64 + 255) // 256 * 256 + items * 16)
             + 255) // 256 * 256
     arena = torch.empty(resident + hip_streams * ctrl + budget, dtype=torch.uint8, device="cuda")
+    refs = [torch.from_numpy(s.view(np.uint8)).to("cuda") for s, _ in corpus]
     srv = Server(arena, resident, hip_streams=hip_streams, max_batch=max_batch, prep_threads=8,
                  items_per_launch=items)
     ids = [srv.add_content(b) for _, b in corpus]
@@ -435,28 +558,53 @@ def run_c4(args, torch, np, rc, synth):
     n_req = int(np.searchsorted(arrivals, warm + dur))
     pick = (synth.splitmix64(0xC4C4, 0, n_req) % np.uint64(len(ids))).astype(np.int64)
     want = [synth.log_uniform_int(0x5D1, i, 1, splits_of[pick[i]]) for i in range(n_req)]
-    verify_every = 97
     rec = {}
-    errors = []
+    verified = [0]
+    vstream = torch.cuda.Stream()
+    # One mismatch flag per request, set on the device by the request's comparison.
+    flags = torch.zeros(n_req, dtype=torch.bool, device="cuda")
     done_evt = threading.Event()
 
     def poller():
+        # Each completed request's output is compared with its content by kernels queued on
+        # a side stream (no host synchronisation per request); the request is released once
+        # an event recorded after its comparison has completed, so the comparisons pipeline
+        # and releases are not held behind one another. (The completion word is written after
+        # a system-scope fence that follows every store of the request, so kernels launched
+        # after it is observed see the whole output.)
+        from collections import deque
+        waiting = deque()          # (event, request ids to release once it has completed)
         got = 0
-        while got < n_req:
-            for c in srv.poll(timeout_us=1000):
-                got += 1
-                rec[c.tag] = (c.t_arrival_ns, c.t_admit_ns, c.t_launch_ns, c.t_done_ns, c.out_bytes, c.status,
-                              c.device_error, c.splits)
-                if c.status == 0:
-                    if c.tag % verify_every == 0:
-                        s = corpus[c.content][0]
-                        if not np.array_equal(srv.output_of(c, s.dtype), s):
-                            errors.append(c.tag)
-                    srv.release(c.request_id)
-            if done_evt.is_set() and got < n_req and time.time() > deadline[0]:
-                break
+        with torch.cuda.stream(vstream):
+            while got < n_req or waiting:
+                ids = []
+                for c in srv.poll(timeout_us=200 if waiting else 1000):
+                    got += 1
+                    rec[c.tag] = (c.t_arrival_ns, c.t_admit_ns, c.t_launch_ns, c.t_done_ns, c.out_bytes, c.status,
+                                  c.device_error, c.splits)
+                    if c.status != 0:
+                        continue
+                    if c.tag % args.c4_verify_every == 0:
+                        out = arena[c.out_offset: c.out_offset + c.out_bytes]
+                        flags[c.tag] = torch.ne(out, refs[c.content]).any()
+                        verified[0] += 1
+                    ids.append(c.request_id)
+                if ids:
+                    ev = torch.cuda.Event()
+                    ev.record(vstream)
+                    waiting.append((ev, ids))
+                while waiting and waiting[0][0].query():
+                    for rid in waiting.popleft()[1]:
+                        srv.release(rid)
+                if done_evt.is_set() and got < n_req and time.time() > deadline[0]:
+                    break
 
     deadline = [float("inf")]
+    # The submitter waits in sleeps only (each releases the GIL), and threads hand the GIL
+    # over every 0.1 ms, so the poller (which verifies and releases every request) never
+    # waits behind a spinning submitter.
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
     th = threading.Thread(target=poller, daemon=True)
     th.start()
     t0 = now_ns() + 20_000_000
@@ -467,17 +615,19 @@ def run_c4(args, torch, np, rc, synth):
             d = due - now_ns()
             if d <= 0:
                 break
-            if d > 300_000:
-                time.sleep((d - 200_000) * 1e-9)
+            time.sleep(d * 1e-9 if d > 100_000 else 0)
         if now_ns() - due > 1_000_000:
             late += 1
         srv.submit(ids[pick[i]], want[i], tag=i, arrival_ns=due)
     done_evt.set()
     deadline[0] = time.time() + 120
     th.join()
+    sys.setswitchinterval(switch)
     st = srv.stats()
     srv.close()
-    lat, win_bytes = [], 0
+    lat, win_bytes, win_words = [], 0, 0
+    parts = {"queue": [], "launch": [], "device": []}
+    by_units = {b: [] for b in LATENCY_BUCKETS}
     t_win0, t_win1 = t0 + int(warm * 1e9), t0 + int((warm + dur) * 1e9)
     bad = 0
     last_done = t_win0
@@ -486,35 +636,74 @@ def run_c4(args, torch, np, rc, synth):
             bad += 1
             continue
         if ta >= t_win0:
-            lat.append((td - ta) * 1e-6)
+            ms = (td - ta) * 1e-6
+            lat.append(ms)
+            parts["queue"].append((tad - ta) * 1e-6)
+            parts["launch"].append((tl - tad) * 1e-6)
+            parts["device"].append((td - tl) * 1e-6)
             win_bytes += ob
+            win_words += 2 * corpus[pick[tag]][1].info.n_words
             last_done = max(last_done, td)
+            for lo, hi in LATENCY_BUCKETS:
+                if lo <= spl <= hi:
+                    by_units[(lo, hi)].append(ms)
     lat = np.array(sorted(lat))
     span = max(t_win1, last_done) - t_win0
     sustained = win_bytes / (span * 1e-9) / 1e9
     offered = float(np.mean([corpus[pick[i]][0].nbytes for i in range(n_req)])) * rate / 1e9
-    q = (lambda p: round(float(np.percentile(lat, p)), 3)) if len(lat) else (lambda p: None)
-    log(f"C4: {len(rec)}/{n_req} completed, window {len(lat)} requests, p50 {q(50)} ms, p99 {q(99)} ms, "
-        f"sustained {sustained:.2f} GB/s (offered {offered:.2f}), late submits {late}, bad {bad}, "
-        f"verify errors {len(errors)}")
+
+    def pct(a, p):
+        return round(float(np.percentile(a, p)), 3) if len(a) else None
+
+    buckets = {}
+    for (lo, hi), v in by_units.items():
+        v = np.array(v)
+        name = f"{lo}" if lo == hi else (f"{lo}-{hi}" if hi < (1 << 40) else f">={lo}")
+        buckets[name] = {"requests": int(len(v)), "p50": pct(v, 50), "p99": pct(v, 99),
+                         "max": round(float(v.max()), 3) if len(v) else None}
+    torch.cuda.synchronize()
+    mismatches = torch.nonzero(flags).flatten().tolist()
+    exact = not mismatches and bad == 0 and len(rec) == n_req and (
+        verified[0] == n_req or args.c4_verify_every > 1)
+    log(f"C4: {len(rec)}/{n_req} completed, window {len(lat)} requests, p50 {pct(lat, 50)} ms, p99 {pct(lat, 99)} "
+        f"ms, sustained {sustained:.2f} GB/s (offered {offered:.2f}), late submits {late}, failed {bad}, "
+        f"verified {verified[0]}, mismatches {len(mismatches)}")
+    cpu = None
+    if not args.no_cpu:
+        first = range(min(n_req, 400))
+        conts = (corpus[pick[i]][1].combine(want[i]).to_bytes() for i in first)
+        syms = (corpus[pick[i]][0] for i in first)
+        cpu = cpu_oracle_streams(conts, np, syms, "the first requests in arrival order, each combined to its "
+                                 "requested split count (host codec containers, byte-identical to the oracle's)")
+        log(f"C4 cpu oracle: {cpu['value']} GB/s")
+    del refs, arena, flags
     return {
-        "metric": METRIC, "value": round(sustained, 3), "unit": "GB/s", "n_gpus": 1, "steps": len(lat),
-        "warmup": int(warm * rate), "ms_per_step": q(50), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic (seeded corpus and Poisson arrivals; the paper's corpora are not available)",
+        "value": round(sustained, 3), "unit": "GB/s", "exact": exact, "dtype": "u32",
+        "latency_ms": {"p50": pct(lat, 50), "p90": pct(lat, 90), "p99": pct(lat, 99), "p99.9": pct(lat, 99.9),
+                       "max": round(float(lat[-1]), 3) if len(lat) else None,
+                       "how": "arrival (scheduled submit time) to the launcher observing the request's "
+                              "completion word, requests arriving in the window"},
+        "latency_by_units_requested": buckets,
+        "latency_parts_ms": {k: {"p50": pct(np.array(v), 50), "p99": pct(np.array(v), 99)} for k, v in parts.items()},
+        "offered_gbs": round(offered, 3),
         "config": {"workload": f"serving: Poisson {rate:g} req/s over a resident corpus of {len(corpus)} streams "
-                               f"(64 KiB-64 MiB, C3 mix, ~1 KiB per stored split), per-request split count "
-                               f"log-uniform in [1, stored], combined at admission, 32 GiB budget, "
-                               f"{hip_streams} HIP streams, up to {max_batch} requests per launch",
-                   "requests": n_req, "window_s": dur, "warmup_s": warm,
-                   "bit_exact": not errors and bad == 0, "verified_requests": n_req // verify_every + 1},
-        "roofline": None,
-        "cpu_baseline": None,
-        "extras": {"latency_ms": {"p50": q(50), "p90": q(90), "p99": q(99), "p99.9": q(99.9),
-                                  "max": round(float(lat[-1]), 3) if len(lat) else None},
-                   "offered_gbs": round(offered, 3), "launches": st.launches,
-                   "requests_per_launch": round(st.requests_launched / max(1, st.launches), 2),
-                   "budget_peak_bytes": st.budget_peak, "late_submits": late, "failed": bad},
+                               f"(sizes at the quantiles of log-uniform 64 KiB-64 MiB, mean "
+                               f"{np.mean([s.nbytes for s, _ in corpus]) / 2**20:.2f} MiB; C3 mix; ~1 KiB per "
+                               f"stored split), per-request split count log-uniform in [1, stored], combined at "
+                               f"admission, 32 GiB budget, {hip_streams} HIP streams, up to {max_batch} requests "
+                               f"per launch",
+                   "requests": n_req, "window_s": dur, "warmup_s": warm, "requests_in_window": int(len(lat)),
+                   "requests_verified": verified[0], "verify_every": args.c4_verify_every,
+                   "verify": "every completed request (verify_every 1): its output range compared with its "
+                             "content on the device before release (kernels on a side stream, one mismatch "
+                             "flag per request, released after the comparison's event)"},
+        "launches": st.launches, "requests_per_launch": round(st.requests_launched / max(1, st.launches), 2),
+        "budget_peak_bytes": st.budget_peak, "late_submits": late, "failed": bad,
+        "roofline": roofline("decode_batch_c4", "decode_batch", win_bytes + win_words, span * 1e-6,
+                             note="sustained over the window: decoded + bitstream bytes of the window's "
+                                  "requests / window span; at this load the chip is mostly idle, so this is "
+                                  "the offered utilisation, not the kernel's efficiency"),
+        "cpu_baseline": cpu,
     }
 
 
@@ -527,15 +716,19 @@ def main():
                     help="interleaved lanes of the headline encoding (the other is reported in extras)")
     ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU[,UNITS_PER_RUN]",
                     help="launch shape of the decode kernel (default 16,8,0,0: units per run chosen at launch)")
-    ap.add_argument("--workload", default="c1", choices=("c1", "c3", "c4"))
+    ap.add_argument("--workload", default="all", choices=("all", "c1", "c3", "c4"),
+                    help="all (default): the headline line with c3 and c4 in it; c1: without them; "
+                         "c3 / c4: that workload's own line")
     ap.add_argument("--c3-streams", type=int, default=4096, help="streams in the batched workload")
     ap.add_argument("--c4-corpus", type=int, default=128, help="resident streams in the serving corpus")
     ap.add_argument("--c4-rate", type=float, default=2000.0, help="request arrival rate (1/s)")
     ap.add_argument("--c4-seconds", type=float, default=30.0, help="measured window after warm-up (s)")
     ap.add_argument("--c4-warmup", type=float, default=5.0, help="warm-up before the window (s)")
-    ap.add_argument("--no-extras", action="store_true", help="skip the W=64 and combined-split runs")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 28, help="symbols in the oracle's sample (default: all)")
+    ap.add_argument("--c4-verify-every", type=int, default=1,
+                    help="compare every k-th request's output with its content (default 1: all)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the W=32, every-split, combined and C0 runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="symbols in the oracle's C1 sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES (for counter calibration)")
     args = ap.parse_args()
@@ -544,6 +737,8 @@ def main():
               "(sharding across GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
+    import gc
+
     import numpy as np
     import torch
 
@@ -551,19 +746,27 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
-    if args.workload in ("c3", "c4"):
-        fn = run_c3 if args.workload == "c3" else run_c4
-        print(json.dumps(fn(args, torch, np, rc, synth)), flush=True)
-        return
     if args.copy_calibration:
         # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
-        # the decode kernel's counters to bytes.
+        # the decode kernels' counters to bytes.
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload in ("c3", "c4"):
+        fn = run_c3 if args.workload == "c3" else run_c4
+        sub = fn(args, torch, np, rc, synth)
+        line = {"metric": METRIC, "value": sub["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": sub.get("ms_per_step", (sub.get("latency_ms") or {}).get("p50")),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+                "data": "synthetic (seeded streams; the paper's corpora are not available)",
+                "config": sub["config"], "roofline": sub["roofline"], "cpu_baseline": sub["cpu_baseline"],
+                "extras": {k: v for k, v in sub.items() if k not in ("value", "unit", "config", "roofline",
+                                                                   "cpu_baseline")}}
+        print(json.dumps(line), flush=True)
+        return
     base = run_c1(args, torch, np, rc, synth)
     extras = {"upload": {"bytes": base["upload_bytes"], "ms": round(base["upload_s"] * 1e3, 3),
                          "first_ms": round(base["upload_cold_s"] * 1e3, 3),
@@ -581,11 +784,11 @@ def main():
             "decoded_gbs": round(other["value"], 2), "ms_per_step": round(other["ms_per_step"], 4),
             "exact": other["exact"], "metadata_bytes": other["blob_info"].metadata_bytes,
             "launch": other["shape"],
-            "roofline": {"bound": "hbm", "achieved": round(other["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(other["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(f"decode_units_c1_w{other_lanes}"),
-                         "alg_bytes_per_launch": other["alg_bytes"],
-                         "kernel_ms_mean": round(other["kernel_ms_mean"], 5)}}
+            "roofline": roofline(f"decode_units_c1_w{other_lanes}", "decode_units", other["alg_bytes"],
+                                 other["kernel_ms_mean"])}
+        for k in ("every_split_point", "cache_cold"):
+            if k in other:
+                extras[f"w{other_lanes}"][k] = other[k]
         w32 = other if other_lanes == 32 else base
         extras["combined_w32"] = run_combined(args, w32, torch, np, rc)
         del other, w32
@@ -593,11 +796,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_oracle_baseline(base["spec"], args.cpu_sample, np)
-        log(f"cpu oracle: {cpu['value']} GB/s on {cpu['cores']} cores")
+        log(f"cpu oracle: {cpu['value']} GB/s on {cpu['cores']} threads ({cpu['timings']})")
 
     info = base["blob_info"]
-    key = f"decode_units_c1_w{args.lanes}"
-    traffic = measured_traffic(key)
+    sh = base["shape"]
     line = {
         "metric": METRIC,
         "value": round(base["value"], 3),
@@ -610,32 +812,35 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic (seeded SplitMix64 Zipf stream; the paper's corpora are not available)",
+        "data": "synthetic (seeded SplitMix64 streams; the paper's corpora are not available)",
         "config": {
             "workload": f"single 256 MiB uint8 stream, Zipf(1.1) over a seeded permutation of 256 symbols, "
-                        f"n=12, W={args.lanes}, {info.splits} splits",
+                        f"n=12, W={args.lanes}, {info.splits} splits, decoded as {sh['runs']} runs of "
+                        f"{sh['units_per_run']} units (Sec. 3.3 combining at launch; every split point: "
+                        f"extras.every_split_point)",
             "n_symbols": info.n_symbols, "n_words": info.n_words, "splits": info.splits,
             "lanes": args.lanes, "quant_bits": info.quant_bits,
             "metadata_bytes": info.metadata_bytes, "container_bytes": info.total_bytes,
-            "bit_exact": base["exact"], "launch": base["shape"],
+            "bit_exact": base["exact"], "launch": sh,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(base["achieved_gbs"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(base["achieved_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "decode_units",
-            "alg_bytes_per_launch": base["alg_bytes"],
-            "kernel_ms_mean": round(base["kernel_ms_mean"], 5),
-            "timing": "mean launch duration of the timed back-to-back decodes (HIP events on the launch stream)",
-            "clock_settle": {"ms": SETTLE_MS, "launches": base["settle_launches"]},
-            "single_launch_ms": {"median": round(base["kernel_ms_median"], 5), "min": round(base["kernel_ms_min"], 5)},
-        },
+        "roofline": roofline(
+            f"decode_units_c1_w{args.lanes}", "decode_units", base["alg_bytes"], base["kernel_ms_mean"],
+            timing="mean launch duration of the timed back-to-back decodes (HIP events on the launch stream)",
+            clock_settle={"ms": SETTLE_MS, "launches": base["settle_launches"]},
+            single_launch_ms={"median": round(base["kernel_ms_median"], 5), "min": round(base["kernel_ms_min"], 5)}),
         "cpu_baseline": cpu,
         "extras": extras,
     }
+    del base
+    gc.collect()
+    torch.cuda.empty_cache()
+    if args.workload == "all":
+        line["c3"] = run_c3(args, torch, np, rc, synth)
+        gc.collect()
+        torch.cuda.empty_cache()
+        line["c4"] = run_c4(args, torch, np, rc, synth)
+        line["config"]["bit_exact_all"] = bool(line["config"]["bit_exact"] and line["c3"]["exact"]
+                                               and line["c4"]["exact"])
     print(json.dumps(line), flush=True)
 
 

@@ -25,7 +25,7 @@ import math
 import os
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
-from typing import Dict, List
+from typing import Dict, List, Optional
 
 import numpy as np
 
@@ -221,16 +221,17 @@ def _log_uniform(u: float, lo: float, hi: float) -> float:
 
 
 def mixed_stream_spec(cfg_seed: int, i: int, lo_bytes: int, hi_bytes: int,
-                      split_bytes: int) -> StreamSpec:
+                      split_bytes: int, size_u: Optional[float] = None) -> StreamSpec:
     """One stream of the mixed batch: size, distribution, alphabet and n drawn per stream.
 
     Sizes are log-uniform in [lo_bytes, hi_bytes] bytes of decoded output; the
     distribution is Laplace (scale 1..32), Zipf (s 0.8..1.5) or uniform with
     equal probability; 3/4 of the streams are uint8 over 256 symbols and 1/4
-    uint16 over 4096 symbols; n is drawn from {10, 11, 12}.
+    uint16 over 4096 symbols; n is drawn from {10, 11, 12}. size_u, if given,
+    replaces the stream's own uniform draw for the size (a quantile in [0, 1)).
     """
     seed = (cfg_seed << 32) + i
-    size = int(_log_uniform(uniform01(seed, 0), lo_bytes, hi_bytes))
+    size = int(_log_uniform(uniform01(seed, 0) if size_u is None else size_u, lo_bytes, hi_bytes))
     kind = ("laplace", "zipf", "uniform")[min(2, int(uniform01(seed, 1) * 3))]
     wide = uniform01(seed, 2) < 0.25
     sym_bytes, A = (2, 4096) if wide else (1, 256)
@@ -255,8 +256,13 @@ def c3_specs(count: int = 4096) -> List[StreamSpec]:
 
 
 def c4_corpus_specs(count: int) -> List[StreamSpec]:
-    """Serving corpus: 64 KiB..64 MiB streams stored with about 1 KiB per split."""
-    return [mixed_stream_spec(4, i, 64 << 10, 64 << 20, 1 << 10) for i in range(count)]
+    """Serving corpus: 64 KiB..64 MiB streams stored with about 1 KiB per split.
+
+    Stream i's size sits at quantile (i + 1/2) / count of the log-uniform size
+    distribution, so that a request drawing a corpus stream uniformly has (up to
+    the midpoint rule) the distribution's mean size, 9.22 MiB; the other draws
+    (distribution, alphabet, n) come from the stream's own seed."""
+    return [mixed_stream_spec(4, i, 64 << 10, 64 << 20, 1 << 10, size_u=(i + 0.5) / count) for i in range(count)]
 
 
 def poisson_arrivals(rate_hz: float, count: int, seed: int = 4) -> np.ndarray:
