@@ -164,13 +164,19 @@ struct PairDecoder {
     uint32_t top0;         // unit 0's first group (the fast body's store base)
     uint32_t top_min;      // smallest first group of the pair's units
     uint32_t steps[S];     // groups the unit decodes
-    int32_t res[S];        // words of the unit still in the ring: (next word + 1) - fq * C
     uint32_t ua[S];        // LDS byte address of the unit's next word in its ring
-    int32_t fq[S];         // lowest chunk held in the ring (the next fetch is fq - 1)
-    uint32_t po[S];        // byte offset from the top third of the third that chunk fq - 1 goes to
     uint32_t presync;      // leading groups of the pair that need the predicated body
     bool sync_lean;        // no unit of the pair is the stream's last (ragged top group, 32-bit states)
-    // Per lane.
+    // Per lane, for the unit of the lane's half-wave: its ring bookkeeping lives in
+    // vector registers, so one instruction keeps both units of a pair up to date and
+    // the scalar registers hold only what the group loop needs.
+    int32_t vres;          // words of the unit still in the ring: (next word + 1) - vfq * C
+    int32_t vfq;           // lowest chunk held in the ring (the next fetch is vfq - 1)
+    uint32_t vpo;          // byte offset from the top third of the third that chunk vfq - 1 goes to
+    // Pairs (S == 2): the LDS byte address of the next word of the lane's unit, the
+    // address at which it wraps, and a mask that confines a read ballot to the
+    // lane's own half-wave.
+    uint32_t vb, vlim, lowmask;
     uint32_t x, rec, act, lim;
     uint32_t my_top, my_ghi, my_steps, lane_off;
     bool active;
@@ -274,7 +280,8 @@ struct PairDecoder {
         active = my_last;
         act = my_last ? 0u : (rec >> 16);
         // Initial fill: the chunk holding word cur-1 and the two below it.
-        int32_t q0[S];
+        int32_t q0[S], fq[S], res[S];
+        uint32_t po[S];
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h) {
             q0[h] = cur[h] > 0 ? (cur[h] - 1) / (int32_t)C : -1;
@@ -283,6 +290,15 @@ struct PairDecoder {
             ua[h] = uni(ring_addr(h, cur[h] > 0 ? (cur[h] - 1) % (int32_t)R : 0));
             po[h] = third_off(fq[h] + 2);      // chunk fq - 1 shares a third with fq + 2
         }
+        const bool hi = S == 2 && upper;
+        vfq = hi ? fq[S - 1] : fq[0];
+        vres = hi ? res[S - 1] : res[0];
+        vpo = hi ? po[S - 1] : po[0];
+        if constexpr (S == 2) {
+            vb = hi ? ua[S - 1] : ua[0];
+            vlim = ring_addr(upper, -1);
+            lowmask = upper ? 0u : 0xFFFFFFFFu;
+        }
 #pragma unroll
         for (uint32_t h = 0; h < S; ++h)
             for (int32_t q = q0[h]; q >= 0 && q > q0[h] - 3; --q)
@@ -290,30 +306,38 @@ struct PairDecoder {
         return any;
     }
 
-    // One group's read step. a (and e, for unit B when W = 32) is the LDS
-    // address of the unit's next word to read; need is this lane's "x < L" (and live).
+    // One group's read step. need is this lane's "x < L" (and live). For one unit
+    // per wave, a is the unit's scalar LDS address of its next word; for a pair, e
+    // is the lane's own unit's address (a vector register), so that the address
+    // chain of a group (ballot, count, address, LDS read) has no scalar step.
     template <uint32_t G_IDX>
     __device__ inline void read_step(bool need, uint32_t &a, uint32_t &e) {
         const uint64_t bal = __ballot(need);
         const uint32_t bl = (uint32_t)bal, bh = (uint32_t)(bal >> 32);
-        const uint32_t m = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl, 0u));
-        // The lane's word is m words above the unit's top word (descending ring).
-        // a/e stay opaque SGPR byte addresses so each address is one v_lshl_add.
-        asm volatile("" : "+s"(a));
-        if constexpr (S == 2) asm volatile("" : "+s"(e));
         uint32_t addr;
         if constexpr (S == 1) {
+            const uint32_t m = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl, 0u));
+            // The lane's word is m words above the unit's top word (descending ring);
+            // a stays an opaque SGPR byte address so the address is one v_lshl_add.
+            asm volatile("" : "+s"(a));
             addr = (m << 1) + a;
             a = s_lshl1_add((uint32_t)__builtin_popcountll(bal), a);
         } else {
-            // Upper lanes' m also counts unit A's readers; unit A's advance cancels them.
-            const uint32_t a_next = s_lshl1_add((uint32_t)__builtin_popcount(bl), a);
-            const uint32_t d = e - a_next;                         // e is unit B's top address
-            uint32_t t = (m << 1) + a;
-            asm volatile("" : "+v"(t));                             // keep v_lshl_add + v_mad_u32_u24
-            addr = __umul24(upper, d) + t;
-            a = a_next;
-            e = s_lshl1_add((uint32_t)__builtin_popcount(bh), e);
+            // Readers below the lane in its own half-wave: the lower half's ballot is
+            // masked off for upper lanes before the count (one v_and with the scalar
+            // ballot; the opaque mask keeps the compiler from turning it into selects).
+            asm volatile("" : "+v"(lowmask));
+            const uint32_t m = __builtin_amdgcn_mbcnt_hi(bh, __builtin_amdgcn_mbcnt_lo(bl & lowmask, 0u));
+            addr = (m << 1) + e;
+            // Each unit's address advances by twice its own readers, off the address
+            // chain of this group: e += 2 pl + upper * 2 (ph - pl). (A VALU instruction
+            // reads at most one scalar operand, so the two counts cannot be selected
+            // per lane in one instruction.)
+            const int32_t pl = __builtin_popcount(bl), ph = __builtin_popcount(bh);
+            const int32_t dd = 2 * (ph - pl);
+            uint32_t t;
+            asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(t) : "v"(upper), "s"(dd), "v"(e));
+            asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(e) : "s"(pl), "v"(t));
         }
         uint32_t w = lds_ld<uint16_t>(addr);
         // Keep the read unconditional: lanes that do not need it read an in-ring word and drop it.
@@ -389,49 +413,40 @@ struct PairDecoder {
     // first word (corrupt split data).
     template <int MODE, uint32_t KK = K>
     __device__ inline bool super_step(uint32_t k) {
-        uint32_t ld = 0;
-#pragma unroll
-        for (uint32_t h = 0; h < S; ++h)
-            if ((MODE != kPred || steps[h] > k) && fq[h] > 0 && res[h] < 2 * (int32_t)C) ld |= 1u << h;
-        uint32_t a = ua[0], e = S == 2 ? ua[S - 1] : 0u;
-        if (ld) {
+        // Per lane: does this lane's unit fetch? (Uniform within each half-wave.)
+        const bool need = (MODE != kPred || my_steps > k) && vfq > 0 && vres < 2 * (int32_t)C;
+        uint32_t a = ua[0], e = S == 2 ? vb : 0u;
+        if (__ballot(need)) {
             // One load for the whole wave, each unit's lanes addressing their own
-            // chunk by a 32-bit byte offset from the scalar bitstream base. The
+            // chunk by a 32-bit byte offset from the scalar bitstream base (lanes of
+            // a unit that does not fetch load an in-range chunk and drop it). The
             // registers stay untouched until the K groups are done; the empty asm
             // keeps the scheduler from hoisting the chunk's use (and its wait on
             // the load) into the groups.
-            uint32_t off = (uint32_t)max(fq[0] - 1, 0) * (2 * C);
-            if constexpr (S == 2) {
-                const uint32_t off_b = (uint32_t)max(fq[1] - 1, 0) * (2 * C);
-                off = upper ? off_b : off;
-            }
+            const uint32_t off = (uint32_t)max(vfq - 1, 0) * (2 * C);
             Chunk pre = *reinterpret_cast<const Chunk *>(reinterpret_cast<const unsigned char *>(p.words) +
                                                          (off + col * (uint32_t)sizeof(Chunk)));
             groups<MODE>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
             asm volatile("" : "+v"(pre));
-#pragma unroll
-            for (uint32_t h = 0; h < S; ++h)
-                if (((ld >> h) & 1u) && (S == 1 || upper == h)) put_chunk(po[h], pre);
+            if (need) {
+                put_chunk(vpo, pre);
+                vfq -= 1;
+                vres += (int32_t)C;
+                vpo = vpo == 4 * C ? 0u : vpo + 2 * C;
+            }
         } else {
             groups<MODE>(std::make_integer_sequence<uint32_t, KK>{}, k, a, e);
         }
-        bool ok = true;
-        uint32_t a_end = a;
-#pragma unroll
-        for (uint32_t h = 0; h < S; ++h) {
-            if (h == 1) a_end = e;
-            // Words consumed from the top-address advance; an address that moved
-            // into the mirror (below slot 0) wraps to the ring's top.
-            res[h] -= (int32_t)((a_end - ua[h]) >> 1);
-            ua[h] = a_end >= ring_addr(h, -1) ? a_end - 2 * R : a_end;
-            if ((ld >> h) & 1u) {
-                fq[h] -= 1;
-                res[h] += (int32_t)C;
-                po[h] = po[h] == 4 * C ? 0u : po[h] + 2 * C;
-            }
-            if (res[h] < 0) ok = false;   // read below the first word: corrupt split data
+        // Words the lane's unit consumed, from its address advance; an address that
+        // moved into the mirror (below slot 0) wraps to the ring's top.
+        if constexpr (S == 1) {
+            vres -= (int32_t)((a - ua[0]) >> 1);
+            ua[0] = a >= ring_addr(0, -1) ? a - 2 * R : a;
+        } else {
+            vres -= (int32_t)((e - vb) >> 1);
+            vb = e >= vlim ? e - 2 * R : e;
         }
-        return ok;
+        return __ballot(vres < 0) == 0;   // read below the first word: corrupt split data
     }
 
     // Decodes one pair. left: pairs of the wave's share after this one.
@@ -481,9 +496,7 @@ struct PairDecoder {
         // otherwise the end runs predicated.
         const uint32_t kend = k < kmax ? k + (kmax - k + K - 1) / K * K : k;
         bool run_on = k <= kmin && top_min + 1 >= kend;
-#pragma unroll
-        for (uint32_t h = 0; h < S; ++h)
-            run_on = run_on && res[h] + fq[h] * (int32_t)C >= (int32_t)((kend - k) * W);
+        run_on = run_on && __ballot(vres + vfq * (int32_t)C < (int32_t)((kend - k) * W)) == 0;
         if (run_on) {
             for (; ok && k < kmax; k += K) {
                 if (8 * k > thr) {
