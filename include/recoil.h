@@ -227,8 +227,13 @@ void recoil_plan_free(recoil_plan *plan);
 /*
  * Decode on the GPU (Sec. 4.1: synchronisation, decoding and cross-boundary
  * phases). Each decode unit runs on W lanes of a 64-lane wavefront (one unit
- * per wave for W = 64, two for W = 32) and writes exactly the whole symbol
- * groups it owns, so every output symbol is written once.
+ * per wave for W = 64, two for W = 32) and writes the whole symbol groups it
+ * owns (Sec. 4.1.3), so every output symbol is written by its owner. Runs of
+ * consecutive units whose states are exact may also decode past their own
+ * groups to the end of their last K-group super-step (the shorter run of a
+ * pair up to its partner's end) and then store the same symbols into the top
+ * groups of the run below: the output is the same, a few groups per run are
+ * stored twice (recoil_decode_count_writes measures it).
  *
  * d_workspace: the uploaded workspace (unchanged by decoding).
  * d_out:       device buffer of N * symbol_bytes bytes, 16-byte aligned.
@@ -241,6 +246,27 @@ void recoil_plan_free(recoil_plan *plan);
  */
 recoil_status recoil_decode(const recoil_plan *plan, const void *d_workspace, void *d_out,
                             uint32_t *d_error, hipStream_t stream);
+
+/*
+ * Checking aid (Sec. 4.1.3 output ownership): recoil_decode with the same
+ * kernels and launch shape, which also adds 1 to d_counts[i] (device uint32,
+ * N entries, zeroed by the caller) for every store of symbol i; slower.
+ * Errors: as recoil_decode; UNSUPPORTED for single-symbol streams (filled
+ * without a decode kernel).
+ */
+recoil_status recoil_decode_count_writes(const recoil_plan *plan, const void *d_workspace, void *d_out,
+                                         uint32_t *d_counts, uint32_t *d_error, hipStream_t stream);
+
+/*
+ * The plan's per-unit records as the decode kernels read them, 4 words per unit
+ * u (0-based; unit u starts at split point u + 1, the last at the final states):
+ * words available (its first read is word next - 1), first group decoded (top,
+ * the anchor), highest group stored (ghi), lowest group decoded and stored (glo).
+ * records = NULL: only *count (the number of units) is set.
+ * cap: capacity of records in units (4 words each).
+ * Errors: INVALID_ARG, BUFFER_TOO_SMALL (cap below the number of units).
+ */
+recoil_status recoil_plan_units(const recoil_plan *plan, uint32_t *records, uint32_t cap, uint32_t *count);
 
 #ifdef __cplusplus
 }

@@ -186,6 +186,25 @@ class Plan:
                                  C.c_void_p(err.data_ptr()), _stream_handle(stream)), "recoil_decode")
 
 
+    def decode_count_writes(self, workspace, out, counts, err, stream=None) -> None:
+        """recoil_decode_count_writes: decode and add 1 to counts[i] (int32 device tensor
+        of N zeros) for every store of symbol i."""
+        if counts.numel() < self.n_symbols or counts.element_size() != 4:
+            raise ValueError("counts must hold N 32-bit words")
+        check(_lib.recoil_decode_count_writes(self._h, C.c_void_p(workspace.data_ptr()),
+                                              C.c_void_p(out.data_ptr()), C.c_void_p(counts.data_ptr()),
+                                              C.c_void_p(err.data_ptr()), _stream_handle(stream)),
+              "recoil_decode_count_writes")
+
+    def units(self) -> np.ndarray:
+        """Per-unit records (units x 4: next, top, ghi, glo) as the kernels read them."""
+        n = C.c_uint32()
+        check(_lib.recoil_plan_units(self._h, None, 0, C.byref(n)), "recoil_plan_units")
+        rec = np.zeros((max(n.value, 1), 4), dtype=np.uint32)
+        check(_lib.recoil_plan_units(self._h, C.c_void_p(rec.ctypes.data), n.value, C.byref(n)), "recoil_plan_units")
+        return rec[: n.value]
+
+
 def decode_blob(blob: Blob, device="cuda"):
     """Convenience: upload, decode and return (symbols tensor, error word)."""
     import torch

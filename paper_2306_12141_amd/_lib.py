@@ -59,6 +59,8 @@ recoil_plan_upload = _sig("recoil_plan_upload", [P, P, sz, P])
 recoil_plan_metadata_device_bytes = _sig("recoil_plan_metadata_device_bytes", [P], sz)
 recoil_plan_free = _sig("recoil_plan_free", [P], None)
 recoil_decode = _sig("recoil_decode", [P, P, P, P, P])
+recoil_decode_count_writes = _sig("recoil_decode_count_writes", [P, P, P, P, P, P])
+recoil_plan_units = _sig("recoil_plan_units", [P, P, u32, C.POINTER(u32)])
 
 
 class RecoilError(RuntimeError):

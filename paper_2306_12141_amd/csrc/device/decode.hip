@@ -26,7 +26,10 @@
 // 16-bit state, at the read step of the group its recorded symbol belongs to,
 // just before its first read. Groups above the unit's own range are decoded
 // only to advance the states. The unit stores groups ghi .. glo (decoding and
-// cross-boundary phases), so each output symbol is written by exactly one unit.
+// cross-boundary phases), so every output symbol is written by the unit that
+// owns it. Once its states are exact, a run may keep decoding whole super-steps
+// past glo (and the shorter run of a pair up to its partner's end); it then also
+// stores the same symbols into the top groups of the run below (the run-on).
 // Super-steps that contain synchronisation, the partial last group or the end
 // of a unit run a predicated body; all others run the unpredicated one.
 #include <algorithm>
@@ -43,10 +46,10 @@ using namespace dev;
 // SS: units per wave. W = 32 runs two units per wave (one per half-wave), or,
 // when the stream has no more units than the grid has waves, one unit per wave
 // with the upper half-wave switched off: then twice as many waves decode.
-template <int W, typename Sym, int K, int WAVES, int SS = 64 / W>
+template <int W, typename Sym, int K, int WAVES, int SS = 64 / W, bool COUNT = false>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET))) void decode_units(
     DecodeParams p) {
-    using D = PairDecoder<W, Sym, K, SS>;
+    using D = PairDecoder<W, Sym, K, SS, COUNT>;
     using L = Lds<0, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
@@ -82,25 +85,25 @@ size_t lds_bytes(uint32_t quant_bits) {
     return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
 }
 
-template <int W, typename Sym, int K, int WAVES, int SS>
+template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
 int units_occupancy(uint32_t quant_bits) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS>, 64 * WAVES,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS, COUNT>, 64 * WAVES,
                                                      lds_bytes<W, Sym, K, WAVES>(quant_bits)) != hipSuccess)
         return 0;
     return per_cu;
 }
 
 // Resident workgroups of the kernel with SS units per wave (0: does not fit).
-template <int W, typename Sym, int K, int WAVES, int SS>
+template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
 uint32_t resident_blocks(const DecodeParams &p, const DecodeTuning &t) {
-    int per_cu = units_occupancy<W, Sym, K, WAVES, SS>(p.quant_bits);
+    int per_cu = units_occupancy<W, Sym, K, WAVES, SS, COUNT>(p.quant_bits);
     if (per_cu < 1) return 0;
     if (t.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)t.blocks_per_cu);
     return (uint32_t)(device_cus() * per_cu);
 }
 
-template <int W, typename Sym, int K, int WAVES, int SS>
+template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
 hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resident, hipStream_t stream,
                      DecodeShape *shape) {
     DecodeParams q = p;
@@ -115,29 +118,29 @@ hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resi
         return hipSuccess;
     }
     const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits);
-    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS, COUNT>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
     return hipGetLastError();
 }
 
-template <int W, typename Sym, int K, int WAVES>
+template <int W, typename Sym, int K, int WAVES, bool COUNT>
 hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     if constexpr (W == 32) {
         // One unit per wave when every run then has a wave of its own: the
         // pair kernel would leave half of those waves idle.
-        const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1>(p, t);
+        const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1, COUNT>(p, t);
         const uint64_t slots = (uint64_t)rs * WAVES;
         const uint32_t k = t.units_per_run ? std::min(t.units_per_run, std::max(p.units, 1u)) : 1u;
         const uint64_t runs = ((uint64_t)p.units + k - 1) / k;
-        if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1>(p, t, rs, stream, shape);
+        if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1, COUNT>(p, t, rs, stream, shape);
     }
-    const uint32_t resident = resident_blocks<W, Sym, K, WAVES, 64 / W>(p, t);
+    const uint32_t resident = resident_blocks<W, Sym, K, WAVES, 64 / W, COUNT>(p, t);
     if (resident == 0) return hipErrorInvalidConfiguration;
-    return launch_ss<W, Sym, K, WAVES, 64 / W>(p, t, resident, stream, shape);
+    return launch_ss<W, Sym, K, WAVES, 64 / W, COUNT>(p, t, resident, stream, shape);
 }
 
 constexpr uint32_t kSimdsPerCu = 4;
 
-template <int W, typename Sym>
+template <int W, typename Sym, bool COUNT>
 hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     if (t.waves == 0) {
         // Automatic: 16 waves per workgroup; one when the launch has no more
@@ -149,20 +152,20 @@ hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_
         DecodeTuning u = t;
         u.waves = 16;
         DecodeShape s{};
-        const hipError_t e = launch_shape<W, Sym>(p, u, stream, &s);
+        const hipError_t e = launch_shape<W, Sym, COUNT>(p, u, stream, &s);
         if (e != hipSuccess) return e;
         const uint64_t pieces = s.units_per_wave ? (s.runs + s.units_per_wave - 1) / s.units_per_wave : 0;
         const uint64_t cus = (uint64_t)device_cus();
         if (pieces <= kSimdsPerCu * cus) u.waves = 1;
         else if (pieces < 16 * cus) u.waves = 8;
-        return launch_shape<W, Sym>(p, u, stream, shape);
+        return launch_shape<W, Sym, COUNT>(p, u, stream, shape);
     }
-    if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 1) return launch_units<W, Sym, 8, 1>(p, t, stream, shape);
-    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16>(p, t, stream, shape);
-    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 1) return launch_units<W, Sym, 8, 1, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16, COUNT>(p, t, stream, shape);
     return hipErrorInvalidValue;
 }
 
@@ -198,10 +201,18 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
     }
-    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t>(p, t, stream, shape);
-    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t>(p, t, stream, shape);
-    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t>(p, t, stream, shape);
-    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t>(p, t, stream, shape);
+    if (p.counts) {
+        // Checking launches: the same kernels, also counting every symbol store.
+        if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, true>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, true>(p, t, stream, shape);
+        if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, true>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, true>(p, t, stream, shape);
+        return hipErrorInvalidValue;
+    }
+    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, false>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, false>(p, t, stream, shape);
+    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, false>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, false>(p, t, stream, shape);
     return hipErrorInvalidValue;
 }
 

@@ -35,6 +35,7 @@ struct DecodeParams {
     const uint32_t *lanes;      // M x W
     void *out;                  // N symbols
     uint32_t *err;              // device error word
+    uint32_t *counts;           // checking launches only: N per-symbol store counts (else NULL)
     uint64_t n_symbols;
     uint32_t units;
     uint32_t run;               // consecutive units decoded as one (Sec. 3.3): 1 uses every split point

@@ -145,7 +145,8 @@ __device__ inline T uni_load(const T *src) {
 // fit are kept in VGPR lanes and mostly reloaded outside the group loops).
 #define RECOIL_SGPR_BUDGET 64
 
-template <int W, typename Sym, int K, int SS = 64 / W>
+// COUNT: a checking build that also adds 1 to counts[i] for every store of symbol i.
+template <int W, typename Sym, int K, int SS = 64 / W, bool COUNT = false>
 struct PairDecoder {
     using G = Geo<W, K, SS>;
     using T = Table<Sym>;
@@ -349,8 +350,12 @@ struct PairDecoder {
     __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh) {
         read_step<G_IDX>(x < kL, a, e);
         const uint32_t s = T::step(lut, x, n, mask);
-        *reinterpret_cast<Sym *>(outh + lane_off - G_IDX * W * sizeof(Sym)) = (Sym)s;
+        unsigned char *dst = outh + lane_off - G_IDX * W * sizeof(Sym);
+        *reinterpret_cast<Sym *>(dst) = (Sym)s;
+        if constexpr (COUNT) count_store((uint64_t)(dst - static_cast<unsigned char *>(p.out)) / sizeof(Sym));
     }
+
+    __device__ inline void count_store(uint64_t i) const { atomicAdd(p.counts + i, 1u); }
 
     template <uint32_t G_IDX>
     __device__ inline void group_pred(uint32_t k, uint32_t &a, uint32_t &e) {
@@ -364,7 +369,10 @@ struct PairDecoder {
         const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
             const uint32_t s = T::step(lut, x, n, mask);
-            if (h <= my_ghi) static_cast<Sym *>(p.out)[i] = (Sym)s;
+            if (h <= my_ghi) {
+                static_cast<Sym *>(p.out)[i] = (Sym)s;
+                if constexpr (COUNT) count_store(i);
+            }
         }
     }
 
@@ -384,7 +392,10 @@ struct PairDecoder {
         asm volatile("" : "+s"(lb));   // the table base as a scalar operand of the address
         const uint32_t s = T::step(lb, x, n, mask);
         const uint32_t h = my_top - k;
-        if (h <= my_ghi) static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
+        if (h <= my_ghi) {
+            static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
+            if constexpr (COUNT) count_store((uint64_t)h * W + coder);
+        }
     }
 
     // Eighths of the share below which priority level L (1..3) ends.

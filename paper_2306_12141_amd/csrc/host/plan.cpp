@@ -276,6 +276,39 @@ recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_o
     return RECOIL_OK;
 }
 
+recoil_status recoil_decode_count_writes(const recoil_plan *plan, const void *d_ws, void *d_out, uint32_t *d_counts,
+                                        uint32_t *d_error, hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws || !d_error || ((!d_out || !d_counts) && plan->d.blob->n_symbols))
+        return fail(RECOIL_ERR_INVALID_ARG, "decode_count_writes: bad arguments");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign ||
+        reinterpret_cast<uintptr_t>(d_counts) % 4)
+        return fail(RECOIL_ERR_ALIGNMENT, "decode_count_writes: misaligned buffer");
+    const PlanData &pl = plan->d;
+    if (pl.single_symbol) return fail(RECOIL_ERR_UNSUPPORTED, "decode_count_writes: single-symbol stream (no decode kernel)");
+    DecodeParams p = decode_params(pl, d_ws, d_out, d_error);
+    p.counts = d_counts;
+    hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_count_writes: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+recoil_status recoil_plan_units(const recoil_plan *plan, uint32_t *records, uint32_t cap, uint32_t *count) {
+    using namespace recoil;
+    if (!plan) return fail(RECOIL_ERR_INVALID_ARG, "plan_units: NULL plan");
+    const std::vector<UnitMeta> &m = plan->d.meta;
+    if (count) *count = (uint32_t)m.size();
+    if (!records) return RECOIL_OK;
+    if (cap < m.size()) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "plan_units: records too small");
+    for (size_t u = 0; u < m.size(); ++u) {
+        records[4 * u + 0] = m[u].next;
+        records[4 * u + 1] = m[u].top;
+        records[4 * u + 2] = m[u].ghi;
+        records[4 * u + 3] = m[u].glo;
+    }
+    return RECOIL_OK;
+}
+
 recoil_status recoil_plan_shape(const recoil_plan *plan, recoil_decode_shape *out) {
     using namespace recoil;
     if (!plan || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_shape: bad arguments");

@@ -184,3 +184,51 @@ def test_single_stream_shapes(rc, shape, lanes, dt):
     torch.cuda.synchronize()
     assert int(err.item()) == 0
     assert np.array_equal(plan.symbols_of(out), s)
+
+
+def _full_size_mix(rc, want_wide=3, want_narrow=5):
+    """Streams of the mixed-batch configuration with sizes drawn from 8..16 MiB, of
+    both table classes (uint8 / uint16 alphabets), about 8 KiB per split."""
+    out, wide, narrow = [], 0, 0
+    for i in range(64):
+        spec = synth.mixed_stream_spec(3, i, 8 << 20, 16 << 20, 8 << 10)
+        is_wide = spec.symbol_bytes == 2
+        if (is_wide and wide >= want_wide) or (not is_wide and narrow >= want_narrow):
+            continue
+        s = spec.generate()
+        present = int(np.count_nonzero(np.bincount(s, minlength=spec.alphabet)))
+        n = max(spec.quant_bits, int(np.ceil(np.log2(max(present, 2)))))
+        out.append((s, rc.encode(s, lanes=32, quant_bits=n, splits=spec.splits, alphabet=spec.alphabet)))
+        wide += is_wide
+        narrow += not is_wide
+        if wide == want_wide and narrow == want_narrow:
+            break
+    assert wide == want_wide and narrow == want_narrow
+    return out
+
+
+def test_batch_full_size_streams(rc):
+    """8..16 MiB streams of the mixed batch in both table classes, each spanning many
+    work items: the autotuned graph replay and the per-stream baseline, every
+    stream compared whole."""
+    from paper_2306_12141_amd.batch import Batch
+    streams = _full_size_mix(rc)
+    batch = Batch([b for _, b in streams])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    best, _ = batch.autotune(ws, out, err, reps=1)
+    _say("full-size batch: items", batch.items, "tuning", best.waves, best.chunk_groups, best.pairs_per_wave,
+         best.units_per_run, "splits", [b.splits for _, b in streams])
+    assert batch.items > 2 * len(streams)
+    g = batch.graph(ws, out, err)
+    for rep in range(2):
+        out.fill_(0x5A if rep else 0xA5)
+        g.launch()
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        _check_all(batch, out, streams)
+    out.fill_(0x3C)
+    batch.decode_per_stream(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    _check_all(batch, out, streams)

@@ -341,3 +341,66 @@ def test_corrupt_offset_sets_error_word(rc, orc):
     plan.decode(ws, out, err)
     torch.cuda.synchronize()
     assert int(err.item()) & 1
+
+
+def _run_on_windows(rec, shape, K):
+    """Groups that each run may store a second time (the run-on below its own lowest
+    group): after synchronisation a run decodes whole K-group super-steps up to its
+    pair's longest run, so at most (kmax - steps) + K - 1 groups below its glo."""
+    M, k, S = len(rec), shape.units_per_run, shape.units_per_wave
+    runs = []
+    for r in range(shape.runs):
+        lo, hi = r * k, min(r * k + k, M) - 1
+        top, glo = int(rec[hi][1]), int(rec[lo][3])
+        runs.append((glo, max(0, top + 1 - glo)))
+    wins = []
+    for r, (glo, steps) in enumerate(runs):
+        mates = runs[r - r % S: r - r % S + S]
+        kmax = max(st for _, st in mates)
+        wins.append((max(0, glo - (kmax - steps) - (K - 1)), glo - 1))
+    return wins
+
+
+@pytest.mark.parametrize("case", ["c0", "w32_pairs", "w64", "u16_pairs", "small_units"])
+def test_write_counts(rc, case):
+    """Every symbol is stored at least once, and a second store happens only in the
+    run-on window of the run above (Sec. 4.1.3 ownership plus the run-on)."""
+    if case == "c0":
+        spec = synth.c0_spec()
+        s, W, n, A, M, kw = spec.generate(), 32, spec.quant_bits, 256, spec.splits, {}
+    elif case == "w32_pairs":
+        s, W, n, A, M, kw = _syms(71, 1 << 23, 256, skew=1.1), 32, 12, 256, 32768, {"units_per_run": 1}
+    elif case == "w64":
+        s, W, n, A, M, kw = _syms(72, 1 << 23, 256, skew=1.1), 64, 12, 256, 16384, {}
+    elif case == "u16_pairs":
+        s, W, n, A, M, kw = _syms(73, (1 << 22) + 77, 4096, np.uint16, 1.05), 32, 12, 4096, 32768, {}
+    else:
+        s, W, n, A, M, kw = _syms(74, 90_001, 256, skew=1.2), 32, 11, 256, 4000, {"units_per_run": 3}
+    blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
+    plan = rc.Plan(blob)
+    K = 8 if s.dtype == np.uint8 else 4
+    if kw:
+        plan.set_tuning(chunk_groups=K, **kw)
+    shape = plan.shape()
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    out.fill_(0x6B)
+    counts = torch.zeros(len(s), dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.decode_count_writes(ws, out, counts, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    assert np.array_equal(plan.symbols_of(out), s)
+    c = counts.cpu().numpy()
+    assert c.min() >= 1, f"{int((c == 0).sum())} symbols never stored"
+    allowed = np.zeros(-(-len(s) // W), dtype=np.int64)
+    for lo, hi in _run_on_windows(plan.units(), shape, K):
+        if hi >= lo:
+            allowed[lo:hi + 1] += 1
+    extra = c.astype(np.int64) - 1
+    limit = np.repeat(allowed, W)[: len(s)]
+    bad = np.nonzero(extra > limit)[0]
+    assert bad.size == 0, f"symbol {bad[0]} stored {c[bad[0]]} times (group {bad[0] // W}, allowed {limit[bad[0]]})"
+    _say(f"{case}: runs {shape.runs} x {shape.units_per_run} units, {shape.units_per_wave} per wave; "
+         f"stored twice {int((c > 1).sum())} of {len(s)} ({(c > 1).mean():.4%})")

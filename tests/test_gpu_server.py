@@ -177,3 +177,43 @@ def test_budget_pressure_and_oversize(rc, corpus):
         _check(srv, corpus, got[r_small])
     finally:
         srv.close()
+
+
+@pytest.fixture(scope="module")
+def big_corpus(rc):
+    """Two serving contents of at least 16 MiB (uint8 and uint16, W = 32), stored with
+    about 1 KiB per split."""
+    out = []
+    for i, (wide, mib) in enumerate([(False, 20), (True, 16)]):
+        A, dt = (4096, np.uint16) if wide else (256, np.uint8)
+        n_sym = (mib << 20) // (2 if wide else 1)
+        s = synth.draw_symbols(synth.laplace_pmf(A, A / 2, 6.0 + 10 * i), 4200 + i, n_sym, dt)
+        present = int(np.count_nonzero(np.bincount(s, minlength=A)))
+        n = max(11, int(np.ceil(np.log2(max(present, 2)))))
+        blob = rc.encode(s, lanes=32, quant_bits=n, splits=-(-s.nbytes // 1024), alphabet=A)
+        out.append((s, blob))
+    return out
+
+
+def test_full_size_requests(rc, big_corpus):
+    """Requests for 16..20 MiB contents combined to one unit, a few units and all units:
+    each alone, then all of them in flight together; every output compared whole."""
+    srv, ids = _server(rc, big_corpus, 512 << 20, hip_streams=3, max_batch=16, items_per_launch=1 << 16)
+    try:
+        asks = [(cid, k) for cid in ids for k in (1, 3, 0)]
+        for cid, k in asks:
+            rid = srv.submit(cid, k, tag=cid)
+            c = _drain(srv, 1, timeout_s=120)[rid]
+            full = big_corpus[cid][1].splits
+            assert c.splits == (full if k == 0 else _combined_units(full, k))
+            _check(srv, big_corpus, c)
+            srv.release(rid)
+        reqs = {srv.submit(cid, k, tag=j): (cid, k) for j, (cid, k) in enumerate(asks + asks)}
+        got = _drain(srv, len(reqs), timeout_s=120)
+        for rid, c in got.items():
+            assert c.content == reqs[rid][0]
+            _check(srv, big_corpus, c)
+            srv.release(rid)
+        assert srv.stats().budget_used == 0
+    finally:
+        srv.close()
