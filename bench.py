@@ -10,6 +10,8 @@ decoded output bytes per second (1 GB = 1e9 B) over the timed steps.
 The same line also carries (each bit-exact against the input symbols):
   extras: the stream at W = 32, every split point used, a decode after evicting
       the caches, the W = 32 stream combined to 16384 / 4096 / 1024 / 256 splits,
+      the same stream coded by the conventional partitioning baseline (Sec. 2.3) at
+      65536 / 16384 / 256 sub-sequences against Recoil at the same parallelism,
       the small Laplace stream, and the host-to-device upload;
   c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8 and uint16,
       n 10..12, about 8 KiB per split) decoded by one hipGraph replay of the
@@ -403,6 +405,36 @@ def run_combined(args, base, torch, np, rc):
     return rows
 
 
+def run_conventional(args, base, torch, np, rc):
+    """The conventional partitioning baseline (Sec. 2.3) on the same stream: P
+    independently coded sub-sequences, decoded by the same kernels (no synchronisation).
+    Compared with the Recoil container combined to the same parallelism: total bytes
+    (what a client receives) and decoded GB/s."""
+    s, recoil_blob, spec = base["symbols"], base["blob"], base["spec"]
+    rows = []
+    for P in (65536, 16384, 256):
+        b = rc.encode_partitioned(s, lanes=spec.lanes, quant_bits=spec.quant_bits, partitions=P)
+        info = b.info
+        plan = rc.Plan(b)
+        ws = plan.allocate_workspace()
+        plan.upload(ws)
+        out = plan.allocate_output()
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        t = time_decode(plan, ws, out, err, max(3, args.steps // 2), 2, torch)
+        exact = check_exact(plan, out, s, err, np)
+        rb = recoil_blob if P >= recoil_blob.info.splits else recoil_blob.combine(P)
+        row = {"partitions": info.splits, "container_bytes": info.total_bytes,
+               "recoil_container_bytes": rb.info.total_bytes, "recoil_splits": rb.info.splits,
+               "saved_by_recoil_bytes": info.total_bytes - rb.info.total_bytes,
+               "decoded_gbs": round(len(s) / (t["ms_per_step"] * 1e-3) / 1e9, 2),
+               "ms": round(t["ms_per_step"], 4), "exact": exact}
+        rows.append(row)
+        log(f"conventional P={info.splits}: {info.total_bytes} B (Recoil {rb.info.total_bytes} B at "
+            f"{rb.info.splits} splits), {row['decoded_gbs']} GB/s, exact={exact}")
+        del ws, out, err, plan, b
+    return rows
+
+
 def _neff(spec, s, np):
     """Quantisation bits able to code every present symbol: max(n, ceil(log2 #present))."""
     present = int(np.count_nonzero(np.bincount(s, minlength=spec.alphabet)))
@@ -791,6 +823,7 @@ def main():
                 extras[f"w{other_lanes}"][k] = other[k]
         w32 = other if other_lanes == 32 else base
         extras["combined_w32"] = run_combined(args, w32, torch, np, rc)
+        extras["conventional_w32"] = run_conventional(args, w32, torch, np, rc)
         del other, w32
         extras["c0"] = run_c0(args, torch, np, rc, synth)
     cpu = None

@@ -47,6 +47,13 @@
  *   (width - 1) field followed by one value of `width` bits per element (signed
  *   series put a sign bit before each magnitude); width = max(1, bit length of
  *   the largest magnitude).
+ *
+ * Conventional partitioned container ("RCP1", the comparison baseline of Sec. 2.3;
+ * recoil_encode_partitioned): the same 48-byte header with magic "RCP1", the
+ * number of sub-sequences P at offset 32 and the sub-sequence length S (symbols,
+ * a multiple of W) at offset 44; then the table; then per sub-sequence q its
+ * first word (u32) and its W final states (u32 each); then the B words of all
+ * sub-sequences, concatenated. Sub-sequence q holds symbols [q S, min((q+1) S, N)).
  */
 #ifndef RECOIL_H
 #define RECOIL_H
@@ -168,12 +175,27 @@ recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoi
                             const uint32_t *freq, uint32_t n_splits, recoil_blob **out);
 
 /*
+ * The conventional "partitioning symbols" baseline (Sec. 2.3), for comparison:
+ * the N symbols are cut into sub-sequences of S = ceil(N / partitions) symbols
+ * rounded up to whole groups of W (so fewer sub-sequences when that covers N),
+ * each encoded on its own by W interleaved coders from state L with the one
+ * table (given, or quantised from the counts of all N symbols), and the
+ * sub-bitstreams are concatenated behind an offset table ("RCP1" above). The
+ * resulting blob plans and decodes like a Recoil blob (every unit starts from
+ * its sub-sequence's final states; there is no synchronisation phase) but its
+ * units cannot be combined (recoil_combine_splits returns UNSUPPORTED).
+ * Errors: INVALID_ARG, INFEASIBLE, UNSUPPORTED (S, P or B not below 2^32).
+ */
+recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
+                                        const uint32_t *freq, uint32_t partitions, recoil_blob **out);
+
+/*
  * Decoder-adaptive combining (Sec. 3.3, end of Sec. 4.2): keep every
  * ceil(M_in / target)-th split point, which leaves ceil(M_in / step) decode
  * units (exactly `target` when it divides M_in), and re-express the stored
  * differences against the new expectations. The bitstream is not touched.
  * target >= M_in returns an equal copy. out: new blob.
- * Errors: INVALID_ARG.
+ * Errors: INVALID_ARG, UNSUPPORTED (a partitioned blob).
  */
 recoil_status recoil_combine_splits(const recoil_blob *in, uint32_t target_splits, recoil_blob **out);
 

@@ -80,6 +80,7 @@ def lib():
         L.orc_series_unpack.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, P, P]
         L.orc_assemble.argtypes = [C.POINTER(Params), C.c_uint64, P, P, C.c_uint64, P, C.c_uint32,
                                    P, P, P, P, C.c_uint64, P]
+        L.orc_encode_partitioned.argtypes = [P, C.c_uint64, C.POINTER(Params), P, C.c_uint32, P, C.c_uint64, P]
         L.orc_info_of.argtypes = [P, C.c_uint64, C.POINTER(Info)]
         L.orc_combine.argtypes = [P, C.c_uint64, C.c_uint32, P, C.c_uint64, P]
         L.orc_open.argtypes = [P, C.c_uint64, C.POINTER(P)]
@@ -195,6 +196,25 @@ def encode(symbols: np.ndarray, p: Params, threads: int, freq: Optional[np.ndarr
                           threads, C.byref(h))
     _check(rc, "encode")
     return Encoded(h, p)
+
+
+def encode_partitioned(symbols: np.ndarray, p: Params, partitions: int,
+                       freq: Optional[np.ndarray] = None) -> bytes:
+    """Conventional partitioned container (Sec. 2.3): independent sub-sequences."""
+    dt = np.uint8 if p.symbol_bytes == 1 else np.uint16
+    symbols = np.ascontiguousarray(symbols, dtype=dt)
+    fp = None
+    if freq is not None:
+        freq = np.ascontiguousarray(freq, dtype=np.uint32)
+        fp = _ptr(freq)
+    n = C.c_uint64()
+    sp = _ptr(symbols) if symbols.size else None
+    _check(lib().orc_encode_partitioned(sp, symbols.size, C.byref(p), fp, partitions, None, 0, C.byref(n)),
+           "encode_partitioned")
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(lib().orc_encode_partitioned(sp, symbols.size, C.byref(p), fp, partitions, _ptr(buf), n.value,
+                                        C.byref(n)), "encode_partitioned")
+    return buf.tobytes()
 
 
 def scan_events(events: List[Tuple[int, int, int, int]], lanes: int, split_event: int):

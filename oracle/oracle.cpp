@@ -142,7 +142,14 @@ struct Stream {
     std::vector<uint16_t> words;      // bitstream B, written forward
     std::vector<uint32_t> final_state;
     std::vector<Split> splits;        // M-1 split points, increasing position
-    uint32_t threads() const { return (uint32_t)splits.size() + 1; }
+    // Conventional partitioning (Sec. 2.3) instead of split points when part_size > 0:
+    // sub-sequence q holds symbols [q S, min((q + 1) S, N)) (S = part_size, a multiple
+    // of W), coded on its own; its words start at part_start[q] and its final states
+    // are part_final[q W .. q W + W - 1].
+    uint64_t part_size = 0;
+    std::vector<uint64_t> part_start;
+    std::vector<uint32_t> part_final;
+    uint32_t threads() const { return part_size ? (uint32_t)part_start.size() : (uint32_t)splits.size() + 1; }
     uint64_t groups() const { return ceil_div(N, p.lanes); }
 };
 
@@ -187,7 +194,42 @@ bool write_metadata(const Stream &st, std::vector<uint8_t> &out) {
     return true;
 }
 
+// Conventional container: the same 48-byte header with magic "RCP1", the number of
+// sub-sequences in the thread field and the sub-sequence length S in the last
+// header word; the table; then per sub-sequence its first word (u32) and W final
+// states (u32 each); then the concatenated words.
+bool write_partitioned(const Stream &st, std::vector<uint8_t> &out) {
+    BitWriter table;
+    std::vector<int64_t> fv(st.f.begin(), st.f.end());
+    if (!put_series(table, fv, 5, false)) return false;
+    const uint32_t P = st.threads(), W = st.p.lanes;
+    out.clear();
+    out.push_back('R'); out.push_back('C'); out.push_back('P'); out.push_back('1');
+    put_le(out, 1, 2);
+    out.push_back((uint8_t)W);
+    out.push_back((uint8_t)st.p.quant_bits);
+    out.push_back((uint8_t)st.p.symbol_bytes);
+    out.push_back((uint8_t)st.p.l_bits);
+    out.push_back((uint8_t)st.p.b_bits);
+    out.push_back(0);
+    put_le(out, st.p.alphabet, 4);
+    put_le(out, st.N, 8);
+    put_le(out, st.words.size(), 8);
+    put_le(out, P, 4);
+    put_le(out, table.bytes.size(), 4);
+    put_le(out, (uint64_t)P * 4 * (1 + W), 4);
+    put_le(out, st.part_size, 4);
+    out.insert(out.end(), table.bytes.begin(), table.bytes.end());
+    for (uint32_t q = 0; q < P; ++q) {
+        put_le(out, st.part_start[q], 4);
+        for (uint32_t j = 0; j < W; ++j) put_le(out, st.part_final[(uint64_t)q * W + j], 4);
+    }
+    for (uint16_t wd : st.words) put_le(out, wd, 2);
+    return true;
+}
+
 bool write_container(const Stream &st, std::vector<uint8_t> &out) {
+    if (st.part_size) return write_partitioned(st, out);
     BitWriter table;
     std::vector<int64_t> fv(st.f.begin(), st.f.end());
     if (!put_series(table, fv, 5, false)) return false;
@@ -216,7 +258,58 @@ bool write_container(const Stream &st, std::vector<uint8_t> &out) {
     return true;
 }
 
+int read_partitioned(const uint8_t *c, uint64_t len, Stream &st, orc_info *info) {
+    st.p.lanes = c[6];
+    st.p.quant_bits = c[7];
+    st.p.symbol_bytes = c[8];
+    st.p.l_bits = c[9];
+    st.p.b_bits = c[10];
+    st.p.alphabet = (uint32_t)get_le(c + 12, 4);
+    if (!params_ok(st.p)) return ORC_CORRUPT;
+    st.N = get_le(c + 16, 8);
+    const uint64_t B = get_le(c + 24, 8);
+    const uint32_t P = (uint32_t)get_le(c + 32, 4);
+    const uint64_t table_bytes = get_le(c + 36, 4);
+    const uint64_t meta_bytes = get_le(c + 40, 4);
+    const uint64_t S = get_le(c + 44, 4);
+    const uint64_t W = st.p.lanes;
+    if (S == 0 || S % W != 0 || P != std::max<uint64_t>(1, ceil_div(st.N, S))) return ORC_CORRUPT;
+    if (meta_bytes != (uint64_t)P * 4 * (1 + W) || B > len || 48 + table_bytes + meta_bytes + 2 * B != len)
+        return ORC_CORRUPT;
+    if (info) {
+        info->n_symbols = st.N; info->n_words = B; info->threads = P;
+        info->lanes = st.p.lanes; info->quant_bits = st.p.quant_bits;
+        info->symbol_bytes = st.p.symbol_bytes; info->alphabet = st.p.alphabet;
+        info->l_bits = st.p.l_bits; info->b_bits = st.p.b_bits;
+        info->table_bytes = table_bytes; info->metadata_bytes = meta_bytes; info->total_bytes = len;
+    }
+    const uint8_t *q = c + 48;
+    BitReader tr{q, table_bytes};
+    std::vector<int64_t> fv;
+    if (!get_series(tr, st.p.alphabet, 5, false, fv) || ceil_div(tr.pos, 8) != table_bytes) return ORC_CORRUPT;
+    uint64_t total = 0;
+    st.f.assign(st.p.alphabet, 0);
+    for (uint32_t s = 0; s < st.p.alphabet; ++s) { st.f[s] = (uint32_t)fv[s]; total += st.f[s]; }
+    if (total != (1ull << st.p.quant_bits)) return ORC_CORRUPT;
+    q += table_bytes;
+    st.part_size = S;
+    st.part_start.resize(P);
+    st.part_final.resize((uint64_t)P * W);
+    for (uint32_t k = 0; k < P; ++k) {
+        st.part_start[k] = get_le(q, 4);
+        q += 4;
+        for (uint64_t j = 0; j < W; ++j, q += 4) st.part_final[(uint64_t)k * W + j] = (uint32_t)get_le(q, 4);
+        if (st.part_start[k] > B || (k > 0 && st.part_start[k] < st.part_start[k - 1])) return ORC_CORRUPT;
+    }
+    if (P && st.part_start[0] != 0) return ORC_CORRUPT;
+    st.splits.clear();
+    st.words.resize(B);
+    for (uint64_t k = 0; k < B; ++k) st.words[k] = (uint16_t)get_le(q + 2 * k, 2);
+    return ORC_OK;
+}
+
 int read_container(const uint8_t *c, uint64_t len, Stream &st, orc_info *info) {
+    if (len >= 48 && std::memcmp(c, "RCP1", 4) == 0 && get_le(c + 4, 2) == 1) return read_partitioned(c, len, st, info);
     if (len < 48 || std::memcmp(c, "RCL1", 4) != 0 || get_le(c + 4, 2) != 1) return ORC_CORRUPT;
     st.p.lanes = c[6];
     st.p.quant_bits = c[7];
@@ -361,6 +454,11 @@ int decode_thread(const Stream &st, uint32_t t, uint64_t lo, uint64_t hi, void *
 }
 
 void thread_range(const Stream &st, uint32_t t, bool aligned, uint64_t &lo, uint64_t &hi) {
+    if (st.part_size) {
+        lo = (uint64_t)(t - 1) * st.part_size;
+        hi = std::min<uint64_t>(st.N, lo + st.part_size);
+        return;
+    }
     const uint32_t M = st.threads();
     const uint64_t W = st.p.lanes;
     auto imin = [&](uint32_t k) -> uint64_t {   // Imin_0 = 0, Imin_M = N
@@ -375,7 +473,46 @@ void thread_range(const Stream &st, uint32_t t, bool aligned, uint64_t &lo, uint
     if (hi < lo) hi = lo;
 }
 
+// Sub-sequence q of a conventional container: plain interleaved decoding of its
+// own words from its own final states (Eq. 2, Eq. 4), symbols [lo, hi).
+int decode_partition(const Stream &st, uint32_t q, void *out) {
+    const uint32_t W = st.p.lanes, n = st.p.quant_bits, b = st.p.b_bits;
+    const uint64_t L = 1ull << st.p.l_bits;
+    const std::vector<uint64_t> F = cdf_of(st.f);
+    const uint64_t lo = (uint64_t)q * st.part_size, hi = std::min<uint64_t>(st.N, lo + st.part_size);
+    const int64_t first = (int64_t)st.part_start[q];
+    const int64_t end = q + 1 < st.threads() ? (int64_t)st.part_start[q + 1] : (int64_t)st.words.size();
+    std::vector<uint64_t> x(W);
+    for (uint32_t j = 0; j < W; ++j) x[j] = st.part_final[(uint64_t)q * W + j];
+    int64_t p = end - 1;
+    const int64_t groups = (int64_t)ceil_div(hi - lo, W);
+    for (int64_t h = groups - 1; h >= 0; --h) {
+        for (uint32_t j = 0; j < W; ++j) {
+            uint64_t i = lo + (uint64_t)h * W + j;
+            if (i < hi) store_symbol(out, st.p.symbol_bytes, i, decode_step(x[j], st.f, F, n));
+        }
+        for (int j = (int)W - 1; j >= 0; --j) {
+            if (x[j] < L) {
+                if (p < first) return ORC_CORRUPT;
+                x[j] = (x[j] << b) | st.words[(uint64_t)p];
+                --p;
+            }
+        }
+    }
+    // Every lane of the sub-sequence started at L and read only its own words.
+    if (p != first - 1) return ORC_CORRUPT;
+    for (uint32_t j = 0; j < W; ++j) if (x[j] != L) return ORC_CORRUPT;
+    return ORC_OK;
+}
+
 int decode_serial(const Stream &st, void *out) {
+    if (st.part_size) {
+        for (uint32_t q = 0; q < st.threads(); ++q) {
+            int rc = decode_partition(st, q, out);
+            if (rc) return rc;
+        }
+        return ORC_OK;
+    }
     const uint32_t W = st.p.lanes, n = st.p.quant_bits, b = st.p.b_bits;
     const uint64_t L = 1ull << st.p.l_bits;
     const std::vector<uint64_t> F = cdf_of(st.f);
@@ -583,6 +720,68 @@ extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp,
 
 extern "C" void orc_enc_free(orc_enc *e) { delete e; }
 
+// Conventional partitioning (Sec. 2.3), the comparison baseline: the symbol sequence
+// is cut into sub-sequences of S symbols (S = ceil(N / P) rounded up to whole groups
+// of W, so every sub-sequence but the last has full groups and lane i mod W), each
+// coded by its own W interleaved encoders from state L (Eq. 1, Eq. 3) with one table
+// for the whole sequence; the sub-bitstreams are concatenated.
+extern "C" int orc_encode_partitioned(const void *symbols, uint64_t N, const orc_params *pp, const uint32_t *freq,
+                                      uint32_t partitions, uint8_t *dst, uint64_t cap, uint64_t *written) {
+    if (!pp || !params_ok(*pp) || partitions < 1 || !written) return ORC_BAD_PARAM;
+    const orc_params P = *pp;
+    Stream st;
+    st.p = P;
+    st.N = N;
+    st.f.assign(P.alphabet, 0);
+    for (uint64_t i = 0; i < N; ++i)
+        if (symbol_at(symbols, P.symbol_bytes, i) >= P.alphabet) return ORC_BAD_PARAM;
+    if (freq) {
+        uint64_t total = 0;
+        for (uint32_t s = 0; s < P.alphabet; ++s) { st.f[s] = freq[s]; total += freq[s]; }
+        if (total != (1ull << P.quant_bits)) return ORC_BAD_PARAM;
+    } else if (N > 0) {
+        std::vector<uint64_t> counts(P.alphabet, 0);
+        for (uint64_t i = 0; i < N; ++i) counts[symbol_at(symbols, P.symbol_bytes, i)]++;
+        int rc = orc_quantize(counts.data(), P.alphabet, P.quant_bits, st.f.data());
+        if (rc) return rc;
+    } else {
+        st.f[0] = 1u << P.quant_bits;
+    }
+    for (uint64_t i = 0; i < N; ++i)
+        if (st.f[symbol_at(symbols, P.symbol_bytes, i)] == 0) return ORC_INFEASIBLE;
+    const std::vector<uint64_t> F = cdf_of(st.f);
+    const uint32_t W = P.lanes, n = P.quant_bits, b = P.b_bits;
+    const uint64_t L = 1ull << P.l_bits;
+    const uint64_t S = std::max<uint64_t>(1, ceil_div(std::max<uint64_t>(ceil_div(N, partitions), 1), W)) * W;
+    const uint64_t parts = std::max<uint64_t>(1, ceil_div(N, S));
+    if (S >= (1ull << 32) || parts >= (1ull << 32)) return ORC_BAD_PARAM;
+    st.part_size = S;
+    for (uint64_t q = 0; q < parts; ++q) {
+        const uint64_t lo = q * S, hi = std::min<uint64_t>(N, lo + S);
+        st.part_start.push_back(st.words.size());
+        std::vector<uint64_t> x(W, L);
+        for (uint64_t i = lo; i < hi; ++i) {
+            const uint32_t j = (uint32_t)((i - lo) % W);
+            const uint32_t s = symbol_at(symbols, P.symbol_bytes, i);
+            const uint64_t fs = st.f[s];
+            if (x[j] >= ((L >> n) << b) * fs) {        // renormalise: low b bits out, then shift
+                st.words.push_back((uint16_t)(x[j] & ((1ull << b) - 1)));
+                x[j] >>= b;
+            }
+            x[j] = ((x[j] / fs) << n) + F[s] + (x[j] % fs);   // Eq. 1
+        }
+        for (uint32_t j = 0; j < W; ++j) st.part_final.push_back((uint32_t)x[j]);
+        if (st.words.size() >= (1ull << 32)) return ORC_BAD_PARAM;
+    }
+    std::vector<uint8_t> c;
+    if (!write_container(st, c)) return ORC_INFEASIBLE;
+    *written = c.size();
+    if (!dst) return ORC_OK;
+    if (cap < c.size()) return ORC_SMALL_BUFFER;
+    std::memcpy(dst, c.data(), c.size());
+    return ORC_OK;
+}
+
 extern "C" uint64_t orc_enc_container_size(const orc_enc *e) {
     std::vector<uint8_t> c;
     if (!write_container(e->st, c)) return 0;
@@ -712,7 +911,7 @@ extern "C" int orc_combine(const uint8_t *c, uint64_t len, uint32_t target, uint
     Stream st;
     int rc = read_container(c, len, st, nullptr);
     if (rc) return rc;
-    if (target < 1) return ORC_BAD_PARAM;
+    if (target < 1 || st.part_size) return ORC_BAD_PARAM;   // sub-sequences cannot be merged (Sec. 2.3)
     const uint32_t M_in = st.threads();
     const uint32_t step = (uint32_t)ceil_div(M_in, std::min(target, M_in));
     std::vector<Split> kept;
@@ -748,6 +947,7 @@ extern "C" int orc_thread_range(const orc_dec *d, uint32_t t, int aligned, uint6
 
 extern "C" int orc_decode_thread(const orc_dec *d, uint32_t t, int aligned, void *out) {
     if (t < 1 || t > d->st.threads()) return ORC_BAD_PARAM;
+    if (d->st.part_size) return decode_partition(d->st, t - 1, out);
     uint64_t lo, hi;
     thread_range(d->st, t, aligned != 0, lo, hi);
     return decode_thread(d->st, t, lo, hi, out);
@@ -755,7 +955,7 @@ extern "C" int orc_decode_thread(const orc_dec *d, uint32_t t, int aligned, void
 
 extern "C" int orc_decode_thread_trace(const orc_dec *d, uint32_t t, int aligned, void *out,
                                       int64_t *decoded, uint64_t cap, uint64_t *count) {
-    if (t < 1 || t > d->st.threads()) return ORC_BAD_PARAM;
+    if (t < 1 || t > d->st.threads() || d->st.part_size) return ORC_BAD_PARAM;
     uint64_t lo, hi;
     thread_range(d->st, t, aligned != 0, lo, hi);
     std::vector<int64_t> trace;

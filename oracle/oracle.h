@@ -99,6 +99,16 @@ int orc_assemble(const orc_params *p, uint64_t n_symbols, const uint32_t *freq,
                  uint32_t threads, const uint64_t *split_pos, const uint32_t *split_states,
                  const int64_t *split_indices, uint8_t *dst, uint64_t cap, uint64_t *written);
 
+/* Conventional partitioning (Sec. 2.3), the comparison baseline: `partitions`
+ * contiguous sub-sequences of S = ceil(N / partitions) symbols rounded up to whole
+ * groups of W (fewer sub-sequences if that covers N), each coded independently
+ * from state L with the one table, sub-bitstreams concatenated. Container magic
+ * "RCP1" (see oracle.cpp). dst = NULL: only *written (the size) is set.
+ * Threads of the decoders below are the sub-sequences; combining is refused. */
+int orc_encode_partitioned(const void *symbols, uint64_t n_symbols, const orc_params *p,
+                           const uint32_t *freq, uint32_t partitions, uint8_t *dst, uint64_t cap,
+                           uint64_t *written);
+
 /* Container-level operations. */
 int orc_info_of(const uint8_t *c, uint64_t len, orc_info *out);
 int orc_combine(const uint8_t *c, uint64_t len, uint32_t target_threads, uint8_t *dst,

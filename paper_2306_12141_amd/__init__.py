@@ -104,6 +104,27 @@ def encode(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, splits: i
     return Blob(h)
 
 
+def encode_partitioned(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, partitions: int = 1,
+                       alphabet: Optional[int] = None, freq: Optional[np.ndarray] = None) -> Blob:
+    """The conventional baseline (Sec. 2.3): `partitions` independently coded sub-sequences
+    (whole groups of `lanes` symbols each) behind an offset table; cannot be combined."""
+    symbols = np.ascontiguousarray(symbols)
+    if symbols.dtype not in (np.uint8, np.uint16):
+        raise TypeError("symbols must be uint8 or uint16")
+    sb = symbols.dtype.itemsize
+    if alphabet is None:
+        alphabet = 256 if sb == 1 else 65536
+    cfg = _lib.Config(lanes, quant_bits, sb, alphabet)
+    fp = None
+    if freq is not None:
+        freq = np.ascontiguousarray(freq, dtype=np.uint32)
+        fp = _ptr(freq)
+    h = C.c_void_p()
+    check(_lib.recoil_encode_partitioned(_ptr(symbols) if symbols.size else None, symbols.size, C.byref(cfg), fp,
+                                         partitions, C.byref(h)), "recoil_encode_partitioned")
+    return Blob(h)
+
+
 def _stream_handle(stream) -> C.c_void_p:
     if stream is None:
         import torch

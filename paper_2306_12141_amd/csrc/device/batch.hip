@@ -76,6 +76,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
         p.single_symbol = d.single_symbol;
+        p.partitioned = d.partitioned;
         if (d.single_symbol) {
             for (uint64_t i = threadIdx.x; i < d.n_symbols; i += 64 * WAVES) {
                 if (d.symbol_bytes == 1) static_cast<uint8_t *>(p.out)[i] = (uint8_t)d.fill_symbol;

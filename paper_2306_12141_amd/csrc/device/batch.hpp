@@ -17,7 +17,7 @@ struct StreamDesc {
     uint32_t units;
     uint8_t quant_bits, symbol_bytes, lanes, single_symbol;
     uint32_t fill_symbol;
-    uint32_t pad;
+    uint32_t partitioned;   // conventional sub-sequences (see DecodeParams::partitioned)
 };
 static_assert(sizeof(StreamDesc) == 64, "StreamDesc is 64 bytes");
 

@@ -109,6 +109,7 @@ hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resi
     DecodeParams q = p;
     q.run = t.units_per_run ? t.units_per_run : auto_units_per_run(p.units, (uint64_t)resident * WAVES * SS);
     q.run = std::min(q.run, std::max(p.units, 1u));
+    if (p.partitioned) q.run = 1;   // independent sub-sequences cannot be decoded as one
     q.runs = (uint32_t)(((uint64_t)p.units + q.run - 1) / q.run);
     const uint32_t pairs = (q.runs + SS - 1) / SS;
     const uint32_t need = (pairs + WAVES - 1) / WAVES;
@@ -129,7 +130,7 @@ hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_
         // pair kernel would leave half of those waves idle.
         const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1, COUNT>(p, t);
         const uint64_t slots = (uint64_t)rs * WAVES;
-        const uint32_t k = t.units_per_run ? std::min(t.units_per_run, std::max(p.units, 1u)) : 1u;
+        const uint32_t k = t.units_per_run && !p.partitioned ? std::min(t.units_per_run, std::max(p.units, 1u)) : 1u;
         const uint64_t runs = ((uint64_t)p.units + k - 1) / k;
         if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1, COUNT>(p, t, rs, stream, shape);
     }

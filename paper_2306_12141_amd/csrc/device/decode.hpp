@@ -43,6 +43,8 @@ struct DecodeParams {
     uint32_t quant_bits;
     uint32_t fill_symbol;       // used when the table holds a single symbol (f = 2^n)
     uint32_t single_symbol;     // nonzero: the stream is one repeated symbol
+    uint32_t partitioned;       // nonzero: conventional sub-sequences (Sec. 2.3): every unit starts
+                                // from its own 32-bit final states, no synchronisation, no run-on
 };
 
 // Launch shape of the single-stream kernel: waves per workgroup (1, 8 or 16;

@@ -247,6 +247,7 @@ struct PairDecoder {
             const uint32_t lo = r * p.run;
             const uint32_t hi = valid ? min(lo + p.run, p.units) - 1u : 0u;
             const bool last = valid && hi + 1 == p.units;
+            const bool full = last || (valid && p.partitioned);   // starts from 32-bit final states
             UnitMeta m = {0, 0, 0, 1};
             if (valid) {
                 m = p.meta[hi];
@@ -258,8 +259,8 @@ struct PairDecoder {
             const uint32_t glo = uni(m.glo);
             steps[h] = (valid && top[h] + 1 > glo) ? top[h] + 1 - glo : 0u;
             uint32_t sync = valid ? top[h] - ghi[h] + 1 : 0u;
-            if (last) sync = (p.n_symbols % W) ? 1u : 0u;
-            has_last = has_last || last;
+            if (full) sync = (last && (p.n_symbols % W)) ? 1u : 0u;   // only the stream's last group is ragged
+            has_last = has_last || full;
             sync_max = max(sync_max, sync);
             any = any || steps[h] > 0;
         }
@@ -275,11 +276,11 @@ struct PairDecoder {
         const uint32_t mine = r0 + upper;
         const bool my_valid = mine < p.runs;
         const uint32_t my_hi = my_valid ? min(mine * p.run + p.run, p.units) - 1u : 0u;
-        const bool my_last = my_valid && my_hi + 1 == p.units;
+        const bool my_full = my_valid && (my_hi + 1 == p.units || p.partitioned);
         rec = my_valid ? p.lanes[(uint64_t)my_hi * W + coder] : 0u;
-        x = my_last ? rec : 0u;
-        active = my_last;
-        act = my_last ? 0u : (rec >> 16);
+        x = my_full ? rec : 0u;
+        active = my_full;
+        act = my_full ? 0u : (rec >> 16);
         // Initial fill: the chunk holding word cur-1 and the two below it.
         int32_t q0[S], fq[S], res[S];
         uint32_t po[S];
@@ -506,7 +507,9 @@ struct PairDecoder {
         // neither below group 0 nor below word 0 (the first units of the stream);
         // otherwise the end runs predicated.
         const uint32_t kend = k < kmax ? k + (kmax - k + K - 1) / K * K : k;
-        bool run_on = k <= kmin && top_min + 1 >= kend;
+        // Independent sub-sequences (Sec. 2.3) never run on: the states do not carry
+        // over into the sub-sequence below.
+        bool run_on = !p.partitioned && k <= kmin && top_min + 1 >= kend;
         run_on = run_on && __ballot(vres + vfq * (int32_t)C < (int32_t)((kend - k) * W)) == 0;
         if (run_on) {
             for (; ok && k < kmax; k += K) {

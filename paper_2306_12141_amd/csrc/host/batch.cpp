@@ -56,6 +56,7 @@ uint32_t pairs_of(const PlanData &pl, uint32_t k) {
 // some idle while others decode long runs.
 uint32_t stream_run(const PlanData &pl, const recoil_tuning &t) {
     const uint32_t M = pl.blob->splits();
+    if (pl.blob->partitioned()) return 1;   // independent sub-sequences: one unit per run
     const uint32_t slots = std::max(1u, t.waves * (pl.blob->lanes == 32 ? 2u : 1u));
     const uint32_t spread = std::max(1u, (M + slots - 1) / slots);
     return run_of(M, std::min(std::max(t.units_per_run, 1u), spread));
@@ -202,6 +203,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
         d.lanes = (uint8_t)bd.lanes;
         d.single_symbol = pl.single_symbol ? 1 : 0;
         d.fill_symbol = pl.fill_symbol;
+        d.partitioned = bd.partitioned() ? 1 : 0;
         b.out_off[i] = out_off;
         b.out_bytes[i] = bd.n_symbols * bd.symbol_bytes;
         out_off = ws_align(out_off + b.out_bytes[i]);
@@ -347,6 +349,7 @@ recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const vo
         p.quant_bits = d.quant_bits;
         p.fill_symbol = d.fill_symbol;
         p.single_symbol = d.single_symbol;
+        p.partitioned = d.partitioned;
         hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
         if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch_per_stream: ") + hipGetErrorString(e));
     }

@@ -32,16 +32,24 @@ struct BlobData {
     std::vector<uint64_t> sp_anchor;     // g_k: largest symbol group among the recorded lanes (0-based)
     std::vector<uint16_t> sp_state;      // (M-1) x W recorded post-shift states (< 2^16, Lemma 3.1)
     std::vector<uint16_t> sp_gdiff;      // (M-1) x W: g_k - group of lane j's recorded symbol
+    // Conventional partitioning (Sec. 2.3) instead of split points when part_size > 0:
+    // sub-sequence q holds symbols [q S, min((q + 1) S, N)) (S = part_size, whole
+    // groups of W), coded on its own from state L; its words start at part_start[q]
+    // and its final states are part_final[q W .. q W + W - 1].
+    uint64_t part_size = 0;
+    std::vector<uint64_t> part_start;
+    std::vector<uint32_t> part_final;
     // Packed sections, computed once.
     std::vector<uint8_t> table_bits;
     std::vector<uint8_t> meta_bits;
 
-    uint32_t splits() const { return (uint32_t)sp_next.size() + 1; }
+    bool partitioned() const { return part_size != 0; }
+    uint32_t splits() const { return partitioned() ? (uint32_t)part_start.size() : (uint32_t)sp_next.size() + 1; }
     uint64_t groups() const { return (n_symbols + lanes - 1) / lanes; }
     const uint16_t *words() const { return words_buf->data(); }
     uint64_t n_words() const { return words_buf->size(); }
     uint64_t total_bytes() const {
-        return 48 + table_bits.size() + 4ull * lanes + meta_bits.size() + 2ull * n_words();
+        return 48 + table_bits.size() + (partitioned() ? 0 : 4ull * lanes) + meta_bits.size() + 2ull * n_words();
     }
     // Symbol index recorded for lane j at split point k (1-based k).
     uint64_t split_index(uint32_t k, uint32_t j) const {

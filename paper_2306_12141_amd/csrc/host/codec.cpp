@@ -329,6 +329,17 @@ bool pack_sections(BlobData &b) {
             return false;
         s.flush();
     }
+    if (b.partitioned()) {
+        // Per sub-sequence: its first word, then its W final states (u32 each).
+        const uint32_t W = b.lanes;
+        b.meta_bits.reserve(b.part_start.size() * 4 * (1 + W));
+        for (size_t q = 0; q < b.part_start.size(); ++q) {
+            if (b.part_start[q] >= (1ull << 32)) return false;
+            put_u(b.meta_bits, b.part_start[q], 4);
+            for (uint32_t j = 0; j < W; ++j) put_u(b.meta_bits, b.part_final[q * W + j], 4);
+        }
+        return true;
+    }
     const uint32_t M = b.splits();
     if (M == 1) return true;
     const uint64_t W = b.lanes;
@@ -391,11 +402,9 @@ recoil_status quantize(const uint64_t *counts, uint32_t A, uint32_t n, uint32_t 
     return RECOIL_OK;
 }
 
-recoil_status encode(const void *symbols, uint64_t N, const recoil_config *cfg, const uint32_t *freq,
-                     uint32_t threads, recoil_blob **out) {
-    if (!out) return fail(RECOIL_ERR_INVALID_ARG, "encode: out is NULL");
-    *out = nullptr;
-    if (!cfg || (N > 0 && !symbols) || threads < 1) return fail(RECOIL_ERR_INVALID_ARG, "encode: bad arguments");
+// Parameters, symbol check and table (given or quantised from the counts) of a new blob.
+recoil_status prepare_blob(const void *symbols, uint64_t N, const recoil_config *cfg, const uint32_t *freq,
+                           std::shared_ptr<BlobData> &out) {
     const uint32_t W = cfg->lanes, n = cfg->quant_bits, sb = cfg->symbol_bytes, A = cfg->alphabet;
     if (W < 1 || W > 64 || n < 1 || n > 16 || (sb != 1 && sb != 2) || A < 1 || A > (sb == 1 ? 256u : 65536u))
         return fail(RECOIL_ERR_INVALID_ARG, "encode: configuration out of range");
@@ -422,11 +431,82 @@ recoil_status encode(const void *symbols, uint64_t N, const recoil_config *cfg, 
     }
     for (uint32_t s = 0; s < A; ++s)
         if (counts[s] && !b->freq[s]) return fail(RECOIL_ERR_INFEASIBLE, "encode: a present symbol has zero frequency");
-    if (sb == 1) encode_stream((const uint8_t *)symbols, *b, threads);
+    out = std::move(b);
+    return RECOIL_OK;
+}
+
+recoil_status encode(const void *symbols, uint64_t N, const recoil_config *cfg, const uint32_t *freq,
+                     uint32_t threads, recoil_blob **out) {
+    if (!out) return fail(RECOIL_ERR_INVALID_ARG, "encode: out is NULL");
+    *out = nullptr;
+    if (!cfg || (N > 0 && !symbols) || threads < 1) return fail(RECOIL_ERR_INVALID_ARG, "encode: bad arguments");
+    std::shared_ptr<BlobData> b;
+    recoil_status st = prepare_blob(symbols, N, cfg, freq, b);
+    if (st) return st;
+    if (b->symbol_bytes == 1) encode_stream((const uint8_t *)symbols, *b, threads);
     else encode_stream((const uint16_t *)symbols, *b, threads);
     if (!pack_sections(*b)) return fail(RECOIL_ERR_INFEASIBLE, "encode: metadata does not fit its series");
     auto *h = new (std::nothrow) recoil_blob();
     if (!h) return fail(RECOIL_ERR_INVALID_ARG, "encode: out of memory");
+    h->data = std::move(b);
+    *out = h;
+    return RECOIL_OK;
+}
+
+namespace {
+
+// One sub-sequence of the conventional baseline: W interleaved coders from state L
+// over symbols [lo, hi) (whole groups from lo, so lane = (i - lo) mod W = i mod W).
+template <typename Sym>
+void encode_part(const Sym *sym, uint64_t lo, uint64_t hi, const std::vector<uint32_t> &F, BlobData &b) {
+    const uint32_t W = b.lanes, n = b.quant_bits;
+    const uint32_t shift = kLowerBits + kWordBits - n;
+    std::vector<uint16_t> &words = *b.words_buf;
+    uint32_t x[64];
+    for (uint32_t j = 0; j < W; ++j) x[j] = kLower;
+    uint32_t j = 0;
+    for (uint64_t i = lo; i < hi; ++i) {
+        const uint32_t s = sym[i], fs = b.freq[s];
+        uint32_t xs = x[j];
+        if ((uint64_t)xs >= ((uint64_t)fs << shift)) {
+            words.push_back((uint16_t)(xs & 0xFFFFu));
+            xs >>= kWordBits;
+        }
+        x[j] = ((xs / fs) << n) + F[s] + (xs % fs);
+        if (++j == W) j = 0;
+    }
+    b.part_final.insert(b.part_final.end(), x, x + W);
+}
+
+}  // namespace
+
+recoil_status encode_partitioned(const void *symbols, uint64_t N, const recoil_config *cfg, const uint32_t *freq,
+                                 uint32_t partitions, recoil_blob **out) {
+    if (!out) return fail(RECOIL_ERR_INVALID_ARG, "encode_partitioned: out is NULL");
+    *out = nullptr;
+    if (!cfg || (N > 0 && !symbols) || partitions < 1)
+        return fail(RECOIL_ERR_INVALID_ARG, "encode_partitioned: bad arguments");
+    std::shared_ptr<BlobData> b;
+    recoil_status st = prepare_blob(symbols, N, cfg, freq, b);
+    if (st) return st;
+    const uint64_t W = b->lanes;
+    const uint64_t S = std::max<uint64_t>(1, cdiv(std::max<uint64_t>(cdiv(N, partitions), 1), W)) * W;
+    const uint64_t P = std::max<uint64_t>(1, cdiv(N, S));
+    if (S >= (1ull << 32) || P >= (1ull << 32)) return fail(RECOIL_ERR_UNSUPPORTED, "encode_partitioned: too large");
+    std::vector<uint32_t> F(b->alphabet + 1, 0);
+    for (uint32_t s = 0; s < b->alphabet; ++s) F[s + 1] = F[s] + b->freq[s];
+    b->part_size = S;
+    b->words_buf->reserve((size_t)(N / 2) + 16);
+    for (uint64_t q = 0; q < P; ++q) {
+        const uint64_t lo = q * S, hi = std::min<uint64_t>(N, lo + S);
+        b->part_start.push_back(b->n_words());
+        if (b->symbol_bytes == 1) encode_part((const uint8_t *)symbols, lo, hi, F, *b);
+        else encode_part((const uint16_t *)symbols, lo, hi, F, *b);
+    }
+    if (b->n_words() >= (1ull << 32) || !pack_sections(*b))
+        return fail(RECOIL_ERR_UNSUPPORTED, "encode_partitioned: bitstream too long for the offset table");
+    auto *h = new (std::nothrow) recoil_blob();
+    if (!h) return fail(RECOIL_ERR_INVALID_ARG, "encode_partitioned: out of memory");
     h->data = std::move(b);
     *out = h;
     return RECOIL_OK;
@@ -456,6 +536,8 @@ std::shared_ptr<BlobData> combine_data(const BlobData &a, uint32_t target) {
 recoil_status combine(const recoil_blob *in, uint32_t target, recoil_blob **out) {
     if (!in || !out || target < 1) return fail(RECOIL_ERR_INVALID_ARG, "combine: bad arguments");
     *out = nullptr;
+    if (in->data->partitioned())
+        return fail(RECOIL_ERR_UNSUPPORTED, "combine: sub-sequences of a partitioned stream cannot be merged");
     std::shared_ptr<BlobData> b = combine_data(*in->data, target);
     if (!b) return fail(RECOIL_ERR_INFEASIBLE, "combine: metadata does not fit its series");
     auto *h = new (std::nothrow) recoil_blob();
@@ -474,7 +556,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     if (cap < total) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "serialize: destination too small");
     std::vector<uint8_t> h;
     h.reserve(48);
-    h.push_back('R'); h.push_back('C'); h.push_back('L'); h.push_back('1');
+    h.push_back('R'); h.push_back('C'); h.push_back(b.partitioned() ? 'P' : 'L'); h.push_back('1');
     put_u(h, 1, 2);
     h.push_back((uint8_t)b.lanes); h.push_back((uint8_t)b.quant_bits); h.push_back((uint8_t)b.symbol_bytes);
     h.push_back((uint8_t)kLowerBits); h.push_back((uint8_t)kWordBits); h.push_back(0);
@@ -484,23 +566,98 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     put_u(h, b.splits(), 4);
     put_u(h, b.table_bits.size(), 4);
     put_u(h, b.meta_bits.size(), 4);
-    put_u(h, 0, 4);
+    put_u(h, b.part_size, 4);
     uint8_t *p = (uint8_t *)dst;
     std::memcpy(p, h.data(), 48);
     p += 48;
     std::memcpy(p, b.table_bits.data(), b.table_bits.size());
     p += b.table_bits.size();
-    for (uint32_t x : b.final_states) { for (int k = 0; k < 4; ++k) *p++ = (uint8_t)(x >> (8 * k)); }
+    if (!b.partitioned())
+        for (uint32_t x : b.final_states) { for (int k = 0; k < 4; ++k) *p++ = (uint8_t)(x >> (8 * k)); }
     if (!b.meta_bits.empty()) std::memcpy(p, b.meta_bits.data(), b.meta_bits.size());
     p += b.meta_bits.size();
     for (uint16_t w : *b.words_buf) { *p++ = (uint8_t)w; *p++ = (uint8_t)(w >> 8); }
     return RECOIL_OK;
 }
 
+namespace {
+
+// The table section: f[s] as a bit series summing to 2^n (Sec. 4.4).
+recoil_status parse_table(const uint8_t *q, uint64_t tbytes, BlobData &b) {
+    BitSource s(q, tbytes);
+    std::vector<int64_t> fv;
+    if (!get_series(s, b.alphabet, 5, false, fv) || cdiv(s.pos(), 8) != tbytes)
+        return fail(RECOIL_ERR_CORRUPT, "container: bad table");
+    uint64_t tot = 0;
+    b.freq.resize(b.alphabet);
+    for (uint32_t k = 0; k < b.alphabet; ++k) {
+        if (fv[k] > (int64_t)(1u << b.quant_bits)) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
+        b.freq[k] = (uint32_t)fv[k];
+        tot += (uint64_t)fv[k];
+    }
+    if (tot != (1ull << b.quant_bits)) return fail(RECOIL_ERR_CORRUPT, "container: table does not sum to 2^n");
+    return RECOIL_OK;
+}
+
+// Conventional container ("RCP1"): the header's thread field counts sub-sequences,
+// its last word is the sub-sequence length S; per sub-sequence its first word and
+// W final states follow the table; then the words.
+recoil_status deserialize_partitioned(const uint8_t *c, size_t len, recoil_blob **out) {
+    auto b = std::make_shared<BlobData>();
+    b->lanes = c[6]; b->quant_bits = c[7]; b->symbol_bytes = c[8];
+    const uint32_t lbits = c[9], wbits = c[10];
+    b->alphabet = (uint32_t)get_u(c + 12, 4);
+    b->n_symbols = get_u(c + 16, 8);
+    const uint64_t B = get_u(c + 24, 8), P = get_u(c + 32, 4);
+    const uint64_t tbytes = get_u(c + 36, 4), mbytes = get_u(c + 40, 4), S = get_u(c + 44, 4);
+    const uint32_t W = b->lanes, n = b->quant_bits, sb = b->symbol_bytes, A = b->alphabet;
+    if (c[11] != 0) return fail(RECOIL_ERR_CORRUPT, "container: reserved byte set");
+    if (W < 1 || W > 64 || n < 1 || n > 16 || (sb != 1 && sb != 2) || A < 1 || A > (sb == 1 ? 256u : 65536u))
+        return fail(RECOIL_ERR_CORRUPT, "container: parameters out of range");
+    if (lbits != kLowerBits || wbits != kWordBits) return fail(RECOIL_ERR_UNSUPPORTED, "container: only L = 2^16, b = 16 supported");
+    if (S == 0 || S % W || P != std::max<uint64_t>(1, cdiv(b->n_symbols, S)))
+        return fail(RECOIL_ERR_CORRUPT, "container: sub-sequence length and count disagree");
+    if (B > len / 2 || tbytes > len || mbytes != P * 4 * (1 + (uint64_t)W) || 48 + tbytes + mbytes + 2 * B != len)
+        return fail(RECOIL_ERR_CORRUPT, "container: length mismatch");
+    const uint8_t *q = c + 48;
+    recoil_status st = parse_table(q, tbytes, *b);
+    if (st) return st;
+    q += tbytes;
+    b->part_size = S;
+    b->part_start.resize(P);
+    b->part_final.resize(P * W);
+    for (uint64_t k = 0; k < P; ++k) {
+        b->part_start[k] = get_u(q, 4);
+        q += 4;
+        if ((k == 0 && b->part_start[0] != 0) || b->part_start[k] > B || (k && b->part_start[k] < b->part_start[k - 1]))
+            return fail(RECOIL_ERR_CORRUPT, "container: sub-bitstream offsets not increasing inside the bitstream");
+        for (uint32_t j = 0; j < W; ++j, q += 4) {
+            b->part_final[k * W + j] = (uint32_t)get_u(q, 4);
+            if (b->part_final[k * W + j] < kLower) return fail(RECOIL_ERR_CORRUPT, "container: final state below L");
+        }
+    }
+    std::vector<uint16_t> &words = *b->words_buf;
+    words.resize(B);
+    for (uint64_t k = 0; k < B; ++k) words[k] = (uint16_t)(q[2 * k] | (q[2 * k + 1] << 8));
+    if (!pack_sections(*b) || b->table_bits.size() != tbytes || b->meta_bits.size() != mbytes)
+        return fail(RECOIL_ERR_CORRUPT, "container: non-canonical table series");
+    auto *h = new (std::nothrow) recoil_blob();
+    if (!h) return fail(RECOIL_ERR_INVALID_ARG, "deserialize: out of memory");
+    h->data = std::move(b);
+    *out = h;
+    return RECOIL_OK;
+}
+
+}  // namespace
+
 recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
     if (!src || !out) return fail(RECOIL_ERR_INVALID_ARG, "deserialize: bad arguments");
     *out = nullptr;
     const uint8_t *c = (const uint8_t *)src;
+    if (len >= 48 && std::memcmp(c, "RCP1", 4) == 0) {
+        if (get_u(c + 4, 2) != 1) return fail(RECOIL_ERR_CORRUPT, "container: unknown version");
+        return deserialize_partitioned(c, len, out);
+    }
     if (len < 48 || std::memcmp(c, "RCL1", 4) != 0) return fail(RECOIL_ERR_CORRUPT, "container: bad magic");
     if (get_u(c + 4, 2) != 1) return fail(RECOIL_ERR_CORRUPT, "container: unknown version");
     auto b = std::make_shared<BlobData>();
@@ -636,6 +793,11 @@ recoil_status recoil_quantize(const uint64_t *counts, uint32_t alphabet, uint32_
 recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                             const uint32_t *freq, uint32_t n_splits, recoil_blob **out) {
     return recoil::encode(symbols, n_symbols, cfg, freq, n_splits, out);
+}
+
+recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
+                                        const uint32_t *freq, uint32_t partitions, recoil_blob **out) {
+    return recoil::encode_partitioned(symbols, n_symbols, cfg, freq, partitions, out);
 }
 
 recoil_status recoil_combine_splits(const recoil_blob *in, uint32_t target_splits, recoil_blob **out) {

@@ -42,6 +42,20 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     const uint64_t G = b.groups();
     pl.meta.resize(M);
     pl.lanes.resize((size_t)M * W);
+    if (b.partitioned()) {
+        // Conventional sub-sequences (Sec. 2.3): unit u decodes sub-sequence u alone,
+        // from its final states over its own words, groups glo .. top.
+        for (uint32_t u = 0; u < M; ++u) {
+            UnitMeta &m = pl.meta[u];
+            const uint64_t lo = (uint64_t)u * b.part_size, hi = std::min<uint64_t>(b.n_symbols, lo + b.part_size);
+            m.glo = (uint32_t)(lo / W);
+            m.top = hi > lo ? (uint32_t)((hi - 1) / W) : m.glo;
+            m.ghi = m.top;
+            m.next = (uint32_t)(u + 1 < M ? b.part_start[u + 1] : b.n_words());
+            for (uint32_t j = 0; j < W; ++j) pl.lanes[(size_t)u * W + j] = b.part_final[(size_t)u * W + j];
+        }
+        return RECOIL_OK;
+    }
     uint32_t prev_sync = 0;
     for (uint32_t u = 0; u < M; ++u) {
         UnitMeta &m = pl.meta[u];
@@ -83,6 +97,7 @@ recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, ui
                                    uint64_t *packed_bytes) {
     const BlobData &b = *bp;
     const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
+    if (b.partitioned()) return fail(RECOIL_ERR_UNSUPPORTED, "combine: sub-sequences cannot be merged");
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
     // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
     if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
@@ -257,6 +272,7 @@ recoil::DecodeParams decode_params(const recoil::PlanData &pl, const void *d_ws,
     p.quant_bits = b.quant_bits;
     p.fill_symbol = pl.fill_symbol;
     p.single_symbol = pl.single_symbol ? 1u : 0u;
+    p.partitioned = b.partitioned() ? 1u : 0u;
     return p;
 }
 

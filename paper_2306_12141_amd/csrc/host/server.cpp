@@ -589,6 +589,8 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
     using namespace recoil;
     if (!s || !blob || !content_id) return fail(RECOIL_ERR_INVALID_ARG, "server_add_content: bad arguments");
     const std::shared_ptr<const BlobData> &bp = blob->data;
+    if (bp->partitioned())   // requests ask for a unit count, which a partitioned stream cannot give
+        return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: partitioned streams cannot be combined per request");
     PlanData probe;
     recoil_status st = build_units(bp, probe);   // checks the GPU decoder's limits
     if (st) return st;

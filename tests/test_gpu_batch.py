@@ -232,3 +232,24 @@ def test_batch_full_size_streams(rc):
     torch.cuda.synchronize()
     assert int(err.item()) == 0
     _check_all(batch, out, streams)
+
+
+def test_batch_with_partitioned_streams(rc, mixed):
+    """Conventional partitioned streams (Sec. 2.3) batched with Recoil streams."""
+    from paper_2306_12141_amd.batch import Batch
+    extra = []
+    for i, (W, N, P, dt) in enumerate([(32, 400_001, 300, np.uint8), (64, 200_000, 64, np.uint16),
+                                       (32, 3_000, 7, np.uint8)]):
+        A = 256 if dt == np.uint8 else 4096
+        s = synth.draw_symbols(synth.zipf_pmf(A, 1.2), 1300 + i, N, dt)
+        extra.append((s, rc.encode_partitioned(s, lanes=W, quant_bits=12, partitions=P, alphabet=A)))
+    streams = mixed[:16] + extra
+    batch = Batch([b for _, b in streams])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    for rep in range(2):
+        out.fill_(0x5A if rep else 0xA5)
+        (batch.decode if rep == 0 else batch.decode_per_stream)(ws, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        _check_all(batch, out, streams)

@@ -404,3 +404,31 @@ def test_write_counts(rc, case):
     assert bad.size == 0, f"symbol {bad[0]} stored {c[bad[0]]} times (group {bad[0] // W}, allowed {limit[bad[0]]})"
     _say(f"{case}: runs {shape.runs} x {shape.units_per_run} units, {shape.units_per_wave} per wave; "
          f"stored twice {int((c > 1).sum())} of {len(s)} ({(c > 1).mean():.4%})")
+
+
+@pytest.mark.parametrize("W,N,P,dt", [(32, 1_000_003, 4096, np.uint8), (64, 1 << 20, 512, np.uint8),
+                                      (32, 300_001, 20_000, np.uint16), (64, 64 * 10_000, 10_000, np.uint16),
+                                      (32, 5_000, 1, np.uint8), (32, 77, 9, np.uint8)])
+def test_partitioned_streams(rc, orc, W, N, P, dt):
+    """The conventional baseline (Sec. 2.3) on the same kernels: every unit starts from
+    its sub-sequence's final states. Checked against the input symbols, and every
+    symbol is stored exactly once (no synchronisation, no run-on)."""
+    A = 256 if dt == np.uint8 else 4096
+    s = _syms(900 + P, N, A, dt, skew=1.1)
+    n = 12
+    blob = rc.encode_partitioned(s, lanes=W, quant_bits=n, partitions=P, alphabet=A)
+    assert blob.to_bytes() == orc.encode_partitioned(
+        s, orc.params(lanes=W, quant_bits=n, symbol_bytes=np.dtype(dt).itemsize, alphabet=A), P)
+    assert np.array_equal(gpu_decode(rc, blob), s)
+    plan = rc.Plan(blob)
+    assert plan.shape().units_per_run == 1
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    counts = torch.zeros(N, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.decode_count_writes(ws, out, counts, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    assert np.array_equal(plan.symbols_of(out), s)
+    assert int(counts.min().item()) == 1 and int(counts.max().item()) == 1

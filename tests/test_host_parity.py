@@ -191,3 +191,48 @@ def test_plan_rejects_unsupported(rc):
     assert e.value.status == -4
     plan = rc.Plan(rc.encode(s, lanes=32, quant_bits=11, splits=4))
     assert plan.device_bytes > 0 and plan.splits == 4
+
+
+@pytest.mark.parametrize("W,N,P,dt", [(32, 100_001, 64, np.uint8), (64, 64 * 300, 300, np.uint8),
+                                      (32, 50_000, 1, np.uint16), (32, 1000, 5000, np.uint8), (64, 0, 3, np.uint8)])
+def test_partitioned_byte_identical(rc, orc, W, N, P, dt):
+    """The conventional baseline (Sec. 2.3): librecoil's container equals the oracle's
+    byte for byte, deserialises to the same bytes, plans one unit per sub-sequence
+    and cannot be combined."""
+    from tests import _fmt
+    A = 256 if dt == np.uint8 else 4096
+    s = _syms(500 + W + P, N, A, dt, skew=1.1)
+    n = 12 if dt == np.uint16 else 11
+    p = orc.params(lanes=W, quant_bits=n, symbol_bytes=np.dtype(dt).itemsize, alphabet=A)
+    ref = orc.encode_partitioned(s, p, P)
+    blob = rc.encode_partitioned(s, lanes=W, quant_bits=n, partitions=P, alphabet=A)
+    assert blob.to_bytes() == ref
+    assert rc.Blob.from_bytes(ref).to_bytes() == ref
+    c = _fmt.parse_partitioned(ref)
+    assert blob.splits == c["P"] and blob.info.metadata_bytes == c["P"] * 4 * (1 + W)
+    units = rc.Plan(blob).units()
+    S = c["S"]
+    for q, (nxt, top, ghi, glo) in enumerate(units):
+        lo, hi = q * S, min(N, (q + 1) * S)
+        assert glo == lo // W and ghi == top and (hi == lo or top == (hi - 1) // W)
+        assert nxt == (c["starts"][q + 1] if q + 1 < c["P"] else c["B"])
+    with pytest.raises(rc.RecoilError):
+        blob.combine(2)
+
+
+def test_partitioned_corruption_rejected(rc, orc):
+    s = _syms(61, 20_000, 256, skew=1.2)
+    good = bytearray(orc.encode_partitioned(s, orc.params(lanes=32, quant_bits=11), 9))
+    for off, val in [(44, 33), (32, 8), (48 + 40, 0xFF), (len(good) - 1, None)]:
+        bad = bytearray(good)
+        if val is None:
+            bad = bad[:-1]
+        elif off == 44:
+            bad[44:48] = (33).to_bytes(4, "little")          # S not a multiple of W
+        elif off == 32:
+            bad[32:36] = (8).to_bytes(4, "little")           # P disagrees with N and S
+        else:
+            hdr = 48 + int.from_bytes(good[36:40], "little")   # first offset must be 0
+            bad[hdr:hdr + 4] = (5).to_bytes(4, "little")
+        with pytest.raises(rc.RecoilError):
+            rc.Blob.from_bytes(bytes(bad))

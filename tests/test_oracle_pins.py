@@ -468,3 +468,90 @@ def test_brute_force_real_parameters_skewed_binary(orc):
     for seq in itertools.product(range(2), repeat=12):
         total += _all_single_splits_decode(orc, p, f, np.array(seq, dtype=np.uint8))
     assert total > 0
+
+
+# ---------------------------------------------------------------------------
+# Conventional partitioning (Sec. 2.3), the comparison baseline
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lanes", [1, 3, 32])
+def test_partitioned_closed_form_words(orc, lanes):
+    """f = 1 at n = 8: every sub-sequence restarts from L, so its words are the
+    closed form of its own symbols (first symbol alone, then byte pairs)."""
+    N = 37 * lanes + 5
+    s = _rng_symbols(50 + lanes, N, 256)
+    p = orc.params(lanes=lanes, quant_bits=8, alphabet=256)
+    c = _fmt.parse_partitioned(orc.encode_partitioned(s, p, 4, freq=np.ones(256, dtype=np.uint32)))
+    S = c["S"]
+    assert S % lanes == 0 and c["P"] == -(-N // S) and S == -(-(-(-N // 4)) // lanes) * lanes
+    for q in range(c["P"]):
+        sub = s[q * S: min(N, (q + 1) * S)]
+        expect = []
+        groups = -(-len(sub) // lanes)
+        for m in range(1, groups, 2):
+            for j in range(lanes):
+                if m * lanes + j >= len(sub):
+                    continue
+                local = sub[j::lanes]
+                expect.append(int(local[0]) if m == 1 else (int(local[m - 2]) << 8) | int(local[m - 1]))
+        assert c["part_words"][q].tolist() == expect, f"sub-sequence {q}"
+    assert np.array_equal(orc.Decoder(orc.encode_partitioned(s, p, 4, freq=np.ones(256, np.uint32))).serial(), s)
+
+
+def test_partitioned_one_part_is_the_plain_stream(orc, c0):
+    """One sub-sequence is plain W-way interleaved rANS: the same words and final
+    states as the Recoil container with one decode unit."""
+    _, s, p, _, _ = c0
+    plain = _fmt.parse(orc.encode(s, p, 1).container())
+    part = _fmt.parse_partitioned(orc.encode_partitioned(s, p, 1))
+    assert part["P"] == 1 and part["S"] >= len(s)
+    assert np.array_equal(part["words"], plain["words"])
+    assert np.array_equal(part["final"][0], plain["final"])
+
+
+def test_partitioned_parts_are_independent_streams(orc, c0):
+    """Each sub-sequence's words and final states are those of a one-unit encoding
+    of that sub-sequence alone with the same table (nothing carries across)."""
+    _, s, p, _, _ = c0
+    f = _fmt_table(orc, s, p)
+    c = _fmt.parse_partitioned(orc.encode_partitioned(s, p, 7, freq=f))
+    S = c["S"]
+    for q in range(c["P"]):
+        alone = _fmt.parse(orc.encode(s[q * S: (q + 1) * S], p, 1, freq=f).container())
+        assert np.array_equal(c["part_words"][q], alone["words"]) and np.array_equal(c["final"][q], alone["final"])
+
+
+def _fmt_table(orc, s, p):
+    counts = np.bincount(s, minlength=p.alphabet).astype(np.uint64)
+    return orc.quantize(counts, p.quant_bits)
+
+
+@pytest.mark.parametrize("lanes,N,P", [(1, 1000, 13), (3, 1001, 7), (32, 100_001, 64), (32, 100_001, 5000),
+                                       (32, 20, 4), (64, 64 * 50, 50), (64, 64 * 50 + 1, 50)])
+def test_partitioned_round_trip(orc, lanes, N, P):
+    s = synth.draw_symbols(synth.zipf_pmf(256, 1.1), 60 + lanes + P, N, np.uint8)
+    p = orc.params(lanes=lanes, quant_bits=11)
+    cont = orc.encode_partitioned(s, p, P)
+    d = orc.Decoder(cont)
+    S = _fmt.parse_partitioned(cont)["S"]
+    assert d.threads == -(-N // S) <= P and S % lanes == 0
+    assert np.array_equal(d.serial(), s) and np.array_equal(d.all(workers=3), s)
+    for t in (1, d.threads):
+        lo, hi = d.thread_range(t)
+        assert (lo, hi) == ((t - 1) * S, min(N, t * S))
+    with pytest.raises(orc.OracleError):
+        orc.combine(cont, 2)
+
+
+def test_partitioned_overhead_per_part(orc):
+    """The cost of partitioning grows linearly with the number of sub-sequences; at
+    W = 32 each extra sub-sequence adds about 93-103 bytes in the paper's
+    Conventional Large variation (Tables 5-6: +203..224 KB over 2176 partitions)."""
+    s = synth.draw_symbols(synth.laplace_pmf(256, 128, 16), 77, 1 << 22, np.uint8)
+    p = orc.params(lanes=32, quant_bits=11)
+    base = len(orc.encode_partitioned(s, p, 1))
+    per = []
+    for P in (256, 2176):
+        per.append((len(orc.encode_partitioned(s, p, P)) - base) / (P - 1))
+    assert all(85 <= v <= 115 for v in per), per
+    assert abs(per[0] - per[1]) / per[1] < 0.1
