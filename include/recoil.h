@@ -48,6 +48,10 @@
  *   series put a sign bit before each magnitude); width = max(1, bit length of
  *   the largest magnitude).
  *
+ * Adaptive container ("RCA1", recoil_encode_adaptive): the Recoil layout above
+ * with magic "RCA1", the number of tables T at offset 44, and a table section
+ * holding T series one after another (table t's f[0..A) in the t-th).
+ *
  * Conventional partitioned container ("RCP1", the comparison baseline of Sec. 2.3;
  * recoil_encode_partitioned): the same 48-byte header with magic "RCP1", the
  * number of sub-sequences P at offset 32 and the sub-sequence length S (symbols,
@@ -175,6 +179,23 @@ recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoi
                             const uint32_t *freq, uint32_t n_splits, recoil_blob **out);
 
 /*
+ * Adaptive coding (Sec. 3.1: the stored symbol indices let each decode unit use a
+ * different distribution for every symbol, keyed by its index). Like
+ * recoil_encode, but symbol i is coded with table table_index[i] of `tables`
+ * tables (freqs: tables x A uint32, table t at t A, each summing to 2^n), in the
+ * renormalisation test and in Eq. 1. The index array is side information the
+ * decoder already holds (as hyperprior-based image codecs derive it); it is not
+ * stored in the container (layout "RCA1" above) and recoil_decode_adaptive takes
+ * it again. Split choice, metadata and combining are those of recoil_encode.
+ * The GPU decodes uint8 symbols with tables x 2^n x 4 <= 64 KiB.
+ * Errors: INVALID_ARG (a table not summing to 2^n, an index >= tables, tables
+ * outside 1..256), INFEASIBLE (a symbol with zero frequency in its table).
+ */
+recoil_status recoil_encode_adaptive(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
+                                     const uint32_t *freqs, uint32_t tables, const uint8_t *table_index,
+                                     uint32_t n_splits, recoil_blob **out);
+
+/*
  * The conventional "partitioning symbols" baseline (Sec. 2.3), for comparison:
  * the N symbols are cut into sub-sequences of S = ceil(N / partitions) symbols
  * rounded up to whole groups of W (so fewer sub-sequences when that covers N),
@@ -268,6 +289,17 @@ void recoil_plan_free(recoil_plan *plan);
  */
 recoil_status recoil_decode(const recoil_plan *plan, const void *d_workspace, void *d_out,
                             uint32_t *d_error, hipStream_t stream);
+
+/*
+ * Decode an adaptive stream (recoil_encode_adaptive): as recoil_decode, with the
+ * per-symbol table index d_table_index (device, N uint8, the array given to the
+ * encoder). Each lane reads its symbol's index at the symbol's output offset and
+ * looks the slot up in that table (one more address operation per symbol; the
+ * decode arithmetic of Eq. 2 is unchanged). recoil_decode refuses adaptive
+ * streams. Errors: INVALID_ARG (not adaptive, NULL index), ALIGNMENT, HIP.
+ */
+recoil_status recoil_decode_adaptive(const recoil_plan *plan, const void *d_workspace, const uint8_t *d_table_index,
+                                     void *d_out, uint32_t *d_error, hipStream_t stream);
 
 /*
  * Checking aid (Sec. 4.1.3 output ownership): recoil_decode with the same

@@ -80,6 +80,9 @@ def lib():
         L.orc_series_unpack.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, P, P]
         L.orc_assemble.argtypes = [C.POINTER(Params), C.c_uint64, P, P, C.c_uint64, P, C.c_uint32,
                                    P, P, P, P, C.c_uint64, P]
+        L.orc_encode_adaptive.argtypes = [P, C.c_uint64, C.POINTER(Params), P, C.c_uint32, P, C.c_uint32,
+                                          C.POINTER(P)]
+        L.orc_set_table_index.argtypes = [P, P, C.c_uint64]
         L.orc_encode_partitioned.argtypes = [P, C.c_uint64, C.POINTER(Params), P, C.c_uint32, P, C.c_uint64, P]
         L.orc_info_of.argtypes = [P, C.c_uint64, C.POINTER(Info)]
         L.orc_combine.argtypes = [P, C.c_uint64, C.c_uint32, P, C.c_uint64, P]
@@ -198,6 +201,21 @@ def encode(symbols: np.ndarray, p: Params, threads: int, freq: Optional[np.ndarr
     return Encoded(h, p)
 
 
+def encode_adaptive(symbols: np.ndarray, p: Params, tables: np.ndarray, tidx: np.ndarray,
+                    threads: int) -> Encoded:
+    """Adaptive coding (Sec. 3.1): tables is (T, A) uint32, symbol i uses table tidx[i]."""
+    dt = np.uint8 if p.symbol_bytes == 1 else np.uint16
+    symbols = np.ascontiguousarray(symbols, dtype=dt)
+    tables = np.ascontiguousarray(tables, dtype=np.uint32)
+    tidx = np.ascontiguousarray(tidx, dtype=np.uint8)
+    assert tables.ndim == 2 and tables.shape[1] == p.alphabet and len(tidx) == len(symbols)
+    h = C.c_void_p()
+    _check(lib().orc_encode_adaptive(_ptr(symbols) if symbols.size else None, symbols.size, C.byref(p),
+                                     _ptr(tables), tables.shape[0], _ptr(tidx) if tidx.size else None, threads,
+                                     C.byref(h)), "encode_adaptive")
+    return Encoded(h, p)
+
+
 def encode_partitioned(symbols: np.ndarray, p: Params, partitions: int,
                        freq: Optional[np.ndarray] = None) -> bytes:
     """Conventional partitioned container (Sec. 2.3): independent sub-sequences."""
@@ -300,6 +318,12 @@ class Decoder:
     @property
     def threads(self) -> int:
         return self.info.threads
+
+    def set_table_index(self, tidx: np.ndarray) -> None:
+        """Adaptive containers: the per-symbol table index decoding needs."""
+        self._tidx = np.ascontiguousarray(tidx, dtype=np.uint8)
+        _check(lib().orc_set_table_index(self._h, _ptr(self._tidx) if self._tidx.size else None, self._tidx.size),
+               "set_table_index")
 
     def _out(self, fill: Optional[int]) -> np.ndarray:
         n = int(self.info.n_symbols)

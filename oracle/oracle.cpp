@@ -149,15 +149,35 @@ struct Stream {
     uint64_t part_size = 0;
     std::vector<uint64_t> part_start;
     std::vector<uint32_t> part_final;
+    // Adaptive coding (Sec. 3.1, third advantage of storing symbol indices): `tables`
+    // frequency tables (f holds tables x A entries) and symbol i coded with table
+    // tidx[i]. The index array is side information both ends hold (as a hyperprior
+    // would give it); it is not part of the container.
+    bool adaptive = false;
+    uint32_t tables = 1;
+    std::vector<uint8_t> tidx;
     uint32_t threads() const { return part_size ? (uint32_t)part_start.size() : (uint32_t)splits.size() + 1; }
     uint64_t groups() const { return ceil_div(N, p.lanes); }
+    uint32_t table_of(uint64_t i) const { return adaptive ? tidx[i] : 0u; }
 };
+
 
 // Cumulative F(s) = sum_{t < s} f(t) (Def. 2.1).
 std::vector<uint64_t> cdf_of(const std::vector<uint32_t> &f) {
     std::vector<uint64_t> F(f.size() + 1, 0);
     for (size_t s = 0; s < f.size(); ++s) F[s + 1] = F[s] + f[s];
     return F;
+}
+
+// Per-table f and F of a stream (one table unless it is adaptive).
+void tables_of(const Stream &st, std::vector<std::vector<uint32_t>> &fs, std::vector<std::vector<uint64_t>> &Fs) {
+    const uint32_t A = st.p.alphabet;
+    fs.assign(st.tables, {});
+    Fs.assign(st.tables, {});
+    for (uint32_t t = 0; t < st.tables; ++t) {
+        fs[t].assign(st.f.begin() + (size_t)t * A, st.f.begin() + (size_t)(t + 1) * A);
+        Fs[t] = cdf_of(fs[t]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -230,13 +250,17 @@ bool write_partitioned(const Stream &st, std::vector<uint8_t> &out) {
 
 bool write_container(const Stream &st, std::vector<uint8_t> &out) {
     if (st.part_size) return write_partitioned(st, out);
+    // One table series, or (adaptive) one per table back to back in one bit stream.
     BitWriter table;
-    std::vector<int64_t> fv(st.f.begin(), st.f.end());
-    if (!put_series(table, fv, 5, false)) return false;
+    for (uint32_t t = 0; t < st.tables; ++t) {
+        std::vector<int64_t> fv(st.f.begin() + (size_t)t * st.p.alphabet,
+                                st.f.begin() + (size_t)(t + 1) * st.p.alphabet);
+        if (!put_series(table, fv, 5, false)) return false;
+    }
     std::vector<uint8_t> meta;
     if (!write_metadata(st, meta)) return false;
     out.clear();
-    out.push_back('R'); out.push_back('C'); out.push_back('L'); out.push_back('1');
+    out.push_back('R'); out.push_back('C'); out.push_back(st.adaptive ? 'A' : 'L'); out.push_back('1');
     put_le(out, 1, 2);
     out.push_back((uint8_t)st.p.lanes);
     out.push_back((uint8_t)st.p.quant_bits);
@@ -250,7 +274,7 @@ bool write_container(const Stream &st, std::vector<uint8_t> &out) {
     put_le(out, st.threads(), 4);
     put_le(out, table.bytes.size(), 4);
     put_le(out, meta.size(), 4);
-    put_le(out, 0, 4);
+    put_le(out, st.adaptive ? st.tables : 0, 4);
     out.insert(out.end(), table.bytes.begin(), table.bytes.end());
     for (uint32_t x : st.final_state) put_le(out, x, 4);
     out.insert(out.end(), meta.begin(), meta.end());
@@ -310,7 +334,11 @@ int read_partitioned(const uint8_t *c, uint64_t len, Stream &st, orc_info *info)
 
 int read_container(const uint8_t *c, uint64_t len, Stream &st, orc_info *info) {
     if (len >= 48 && std::memcmp(c, "RCP1", 4) == 0 && get_le(c + 4, 2) == 1) return read_partitioned(c, len, st, info);
-    if (len < 48 || std::memcmp(c, "RCL1", 4) != 0 || get_le(c + 4, 2) != 1) return ORC_CORRUPT;
+    if (len < 48 || get_le(c + 4, 2) != 1) return ORC_CORRUPT;
+    st.adaptive = std::memcmp(c, "RCA1", 4) == 0;
+    if (!st.adaptive && std::memcmp(c, "RCL1", 4) != 0) return ORC_CORRUPT;
+    st.tables = st.adaptive ? (uint32_t)get_le(c + 44, 4) : 1u;
+    if (st.tables < 1 || st.tables > 256) return ORC_CORRUPT;
     st.p.lanes = c[6];
     st.p.quant_bits = c[7];
     st.p.symbol_bytes = c[8];
@@ -336,13 +364,18 @@ int read_container(const uint8_t *c, uint64_t len, Stream &st, orc_info *info) {
     }
     const uint8_t *q = c + 48;
     BitReader tr{q, table_bytes};
-    std::vector<int64_t> fv;
-    if (!get_series(tr, st.p.alphabet, 5, false, fv)) return ORC_CORRUPT;
+    st.f.assign((size_t)st.tables * st.p.alphabet, 0);
+    for (uint32_t t = 0; t < st.tables; ++t) {
+        std::vector<int64_t> fv;
+        if (!get_series(tr, st.p.alphabet, 5, false, fv)) return ORC_CORRUPT;
+        uint64_t total = 0;
+        for (uint32_t s = 0; s < st.p.alphabet; ++s) {
+            st.f[(size_t)t * st.p.alphabet + s] = (uint32_t)fv[s];
+            total += (uint64_t)fv[s];
+        }
+        if (total != (1ull << st.p.quant_bits)) return ORC_CORRUPT;
+    }
     if (ceil_div(tr.pos, 8) != table_bytes) return ORC_CORRUPT;
-    uint64_t total = 0;
-    st.f.assign(st.p.alphabet, 0);
-    for (uint32_t s = 0; s < st.p.alphabet; ++s) { st.f[s] = (uint32_t)fv[s]; total += st.f[s]; }
-    if (total != (1ull << st.p.quant_bits)) return ORC_CORRUPT;
     q += table_bytes;
     st.final_state.resize(W);
     for (uint64_t j = 0; j < W; ++j) st.final_state[j] = (uint32_t)get_le(q + 4 * j, 4);
@@ -410,10 +443,13 @@ uint32_t decode_step(uint64_t &x, const std::vector<uint32_t> &f, const std::vec
 // phase); symbols are kept only inside [lo, hi).
 int decode_thread(const Stream &st, uint32_t t, uint64_t lo, uint64_t hi, void *out,
                   std::vector<int64_t> *trace = nullptr) {
+    if (st.adaptive && st.tidx.size() != st.N) return ORC_BAD_PARAM;   // the table index is not set
     const uint32_t W = st.p.lanes, n = st.p.quant_bits, b = st.p.b_bits;
     const uint64_t L = 1ull << st.p.l_bits;
     const uint32_t M = st.threads();
-    const std::vector<uint64_t> F = cdf_of(st.f);
+    std::vector<std::vector<uint32_t>> fs;
+    std::vector<std::vector<uint64_t>> Fs;
+    tables_of(st, fs, Fs);
     std::vector<uint64_t> x(W, 0);
     std::vector<bool> active(W, false);
     std::vector<int64_t> init_group(W, 0);
@@ -444,7 +480,8 @@ int decode_thread(const Stream &st, uint32_t t, uint64_t lo, uint64_t hi, void *
         for (uint32_t j = 0; j < W; ++j) {
             uint64_t i = (uint64_t)h * W + j;
             if (!active[j] || i >= st.N) continue;
-            uint32_t s = decode_step(x[j], st.f, F, n);
+            const uint32_t ti = st.table_of(i);
+            uint32_t s = decode_step(x[j], fs[ti], Fs[ti], n);
             if (trace) trace->push_back((int64_t)i);
             if (i >= lo && i < hi) store_symbol(out, st.p.symbol_bytes, i, s);
         }
@@ -513,15 +550,20 @@ int decode_serial(const Stream &st, void *out) {
         }
         return ORC_OK;
     }
+    if (st.adaptive && st.tidx.size() != st.N) return ORC_BAD_PARAM;
     const uint32_t W = st.p.lanes, n = st.p.quant_bits, b = st.p.b_bits;
     const uint64_t L = 1ull << st.p.l_bits;
-    const std::vector<uint64_t> F = cdf_of(st.f);
+    std::vector<std::vector<uint32_t>> fs;
+    std::vector<std::vector<uint64_t>> Fs;
+    tables_of(st, fs, Fs);
     std::vector<uint64_t> x(st.final_state.begin(), st.final_state.end());
     int64_t p = (int64_t)st.words.size() - 1;
     for (int64_t h = (int64_t)st.groups() - 1; h >= 0; --h) {
         for (uint32_t j = 0; j < W; ++j) {
             uint64_t i = (uint64_t)h * W + j;
-            if (i < st.N) store_symbol(out, st.p.symbol_bytes, i, decode_step(x[j], st.f, F, n));
+            if (i >= st.N) continue;
+            const uint32_t ti = st.table_of(i);
+            store_symbol(out, st.p.symbol_bytes, i, decode_step(x[j], fs[ti], Fs[ti], n));
         }
         for (int j = (int)W - 1; j >= 0; --j) {     // read step before group h-1
             if (x[j] < L) {
@@ -596,20 +638,42 @@ extern "C" int orc_quantize(const uint64_t *counts, uint32_t A, uint32_t n, uint
     return ORC_OK;
 }
 
-extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp, const uint32_t *freq,
-                          uint32_t threads, orc_enc **out) {
+namespace {
+
+int encode_body(const void *symbols, orc_enc *e, uint32_t threads, orc_enc **out);
+
+// Recoil encoding (Sec. 4). tidx == NULL: one table (given, or quantised from the
+// counts). Otherwise adaptive coding: T given tables and symbol i coded with table
+// tidx[i] (Sec. 3.1); everything else is the same.
+int encode_impl(const void *symbols, uint64_t N, const orc_params *pp, const uint32_t *freq, uint32_t T,
+                const uint8_t *tidx, uint32_t threads, orc_enc **out) {
     *out = nullptr;
     if (!pp || !params_ok(*pp) || threads < 1) return ORC_BAD_PARAM;
+    if (tidx && (!freq || T < 1 || T > 256)) return ORC_BAD_PARAM;
     const orc_params P = *pp;
     auto *e = new (std::nothrow) orc_enc();
     if (!e) return ORC_BAD_PARAM;
     Stream &st = e->st;
     st.p = P;
     st.N = N;
+    for (uint64_t i = 0; i < N; ++i)
+        if (symbol_at(symbols, P.symbol_bytes, i) >= P.alphabet || (tidx && tidx[i] >= T)) { delete e; return ORC_BAD_PARAM; }
+    if (tidx) {
+        st.adaptive = true;
+        st.tables = T;
+        st.tidx.assign(tidx, tidx + N);
+        st.f.assign(freq, freq + (size_t)T * P.alphabet);
+        for (uint32_t t = 0; t < T; ++t) {
+            uint64_t total = 0;
+            for (uint32_t s = 0; s < P.alphabet; ++s) total += st.f[(size_t)t * P.alphabet + s];
+            if (total != (1ull << P.quant_bits)) { delete e; return ORC_BAD_PARAM; }
+        }
+        for (uint64_t i = 0; i < N; ++i)
+            if (st.f[(size_t)tidx[i] * P.alphabet + symbol_at(symbols, P.symbol_bytes, i)] == 0) { delete e; return ORC_INFEASIBLE; }
+        return encode_body(symbols, e, threads, out);
+    }
     // Table: given, or quantised from the symbol counts.
     st.f.assign(P.alphabet, 0);
-    for (uint64_t i = 0; i < N; ++i)
-        if (symbol_at(symbols, P.symbol_bytes, i) >= P.alphabet) { delete e; return ORC_BAD_PARAM; }
     if (freq) {
         uint64_t total = 0;
         for (uint32_t s = 0; s < P.alphabet; ++s) { st.f[s] = freq[s]; total += freq[s]; }
@@ -624,7 +688,34 @@ extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp,
     }
     for (uint64_t i = 0; i < N; ++i)
         if (st.f[symbol_at(symbols, P.symbol_bytes, i)] == 0) { delete e; return ORC_INFEASIBLE; }
-    const std::vector<uint64_t> F = cdf_of(st.f);
+    return encode_body(symbols, e, threads, out);
+}
+
+}  // namespace
+
+extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp, const uint32_t *freq,
+                          uint32_t threads, orc_enc **out) {
+    return encode_impl(symbols, N, pp, freq, 1, nullptr, threads, out);
+}
+
+extern "C" int orc_encode_adaptive(const void *symbols, uint64_t N, const orc_params *pp, const uint32_t *freqs,
+                                   uint32_t tables, const uint8_t *tidx, uint32_t threads, orc_enc **out) {
+    if (!tidx && N > 0) return ORC_BAD_PARAM;
+    static const uint8_t none = 0;
+    return encode_impl(symbols, N, pp, freqs, tables, tidx ? tidx : &none, threads, out);
+}
+
+namespace {
+
+// The encoder proper, once the table(s) are set: interleaved coding, candidate
+// scan, split choice and the backward scan of each chosen split.
+int encode_body(const void *symbols, orc_enc *e, uint32_t threads, orc_enc **out) {
+    Stream &st = e->st;
+    const orc_params P = st.p;
+    const uint64_t N = st.N;
+    std::vector<std::vector<uint32_t>> fs;
+    std::vector<std::vector<uint64_t>> Fs;
+    tables_of(st, fs, Fs);
 
     // Interleaved encode (Eq. 1 with the renormalisation of Eq. 3, Sec. 2.2).
     const uint32_t W = P.lanes, n = P.quant_bits, b = P.b_bits;
@@ -636,17 +727,19 @@ extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp,
             uint64_t i = g * W + j;
             if (i >= N) break;
             uint32_t s = symbol_at(symbols, P.symbol_bytes, i);
-            uint64_t fs = st.f[s];
+            const uint32_t ti = st.table_of(i);
+            const std::vector<uint64_t> &F = Fs[ti];
+            uint64_t fs_ = fs[ti][s];
             // Renormalise against the frequency of the symbol about to be encoded:
             // emit the low b bits, then shift (the paper prints these two
             // assignments in the opposite order).
-            if (x[j] >= ((L >> n) << b) * fs) {
+            if (x[j] >= ((L >> n) << b) * fs_) {
                 st.words.push_back((uint16_t)(x[j] & ((1ull << b) - 1)));
                 x[j] >>= b;
                 e->ev_idx.push_back((int64_t)i - (int64_t)W);   // the lane's previous symbol
                 e->ev_state.push_back((uint32_t)x[j]);
             }
-            x[j] = ((x[j] / fs) << n) + F[s] + (x[j] % fs);     // Eq. 1
+            x[j] = ((x[j] / fs_) << n) + F[s] + (x[j] % fs_);   // Eq. 1
         }
     }
     st.final_state.assign(x.begin(), x.end());
@@ -718,7 +811,16 @@ extern "C" int orc_encode(const void *symbols, uint64_t N, const orc_params *pp,
     return ORC_OK;
 }
 
+}  // namespace
+
 extern "C" void orc_enc_free(orc_enc *e) { delete e; }
+
+extern "C" int orc_set_table_index(orc_dec *d, const uint8_t *tidx, uint64_t n) {
+    if (!d || !d->st.adaptive || n != d->st.N || (n && !tidx)) return ORC_BAD_PARAM;
+    for (uint64_t i = 0; i < n; ++i) if (tidx[i] >= d->st.tables) return ORC_BAD_PARAM;
+    d->st.tidx.assign(tidx, tidx + n);
+    return ORC_OK;
+}
 
 // Conventional partitioning (Sec. 2.3), the comparison baseline: the symbol sequence
 // is cut into sub-sequences of S symbols (S = ceil(N / P) rounded up to whole groups

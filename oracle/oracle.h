@@ -65,6 +65,13 @@ typedef struct orc_enc orc_enc;
 int orc_encode(const void *symbols, uint64_t n_symbols, const orc_params *p,
                const uint32_t *freq /* NULL: quantise from the data */,
                uint32_t threads, orc_enc **out);
+/* Adaptive coding (Sec. 3.1): `tables` frequency tables (freqs: tables x alphabet,
+ * each summing to 2^n) and symbol i coded with table tidx[i] (< tables). The
+ * container (magic "RCA1") carries the tables; the index array is side information
+ * that decoding needs again (orc_set_table_index). */
+int orc_encode_adaptive(const void *symbols, uint64_t n_symbols, const orc_params *p,
+                        const uint32_t *freqs, uint32_t tables, const uint8_t *tidx,
+                        uint32_t threads, orc_enc **out);
 void orc_enc_free(orc_enc *e);
 uint64_t orc_enc_container_size(const orc_enc *e);
 int orc_enc_container(const orc_enc *e, uint8_t *dst, uint64_t cap);
@@ -117,6 +124,8 @@ int orc_combine(const uint8_t *c, uint64_t len, uint32_t target_threads, uint8_t
 typedef struct orc_dec orc_dec;
 int orc_open(const uint8_t *c, uint64_t len, orc_dec **out);
 void orc_close(orc_dec *d);
+/* Adaptive containers only: the per-symbol table index (n = N entries, each < tables). */
+int orc_set_table_index(orc_dec *d, const uint8_t *tidx, uint64_t n);
 /* Serial interleaved decode of the whole stream; checks end states and cursor. */
 int orc_decode_serial(const orc_dec *d, void *out);
 /* Thread t (1..M) writes only its own output range of the N-symbol buffer.

@@ -104,6 +104,27 @@ def encode(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, splits: i
     return Blob(h)
 
 
+def encode_adaptive(symbols: np.ndarray, tables: np.ndarray, table_index: np.ndarray, lanes: int = 32,
+                    quant_bits: int = 11, splits: int = 1, alphabet: Optional[int] = None) -> Blob:
+    """Adaptive coding (Sec. 3.1): symbol i coded with tables[table_index[i]] (tables: T x A)."""
+    symbols = np.ascontiguousarray(symbols)
+    if symbols.dtype not in (np.uint8, np.uint16):
+        raise TypeError("symbols must be uint8 or uint16")
+    tables = np.ascontiguousarray(tables, dtype=np.uint32)
+    tidx = np.ascontiguousarray(table_index, dtype=np.uint8)
+    if tables.ndim != 2 or len(tidx) != len(symbols):
+        raise ValueError("tables must be T x A and table_index one entry per symbol")
+    sb = symbols.dtype.itemsize
+    if alphabet is None:
+        alphabet = tables.shape[1]
+    cfg = _lib.Config(lanes, quant_bits, sb, alphabet)
+    h = C.c_void_p()
+    check(_lib.recoil_encode_adaptive(_ptr(symbols) if symbols.size else None, symbols.size, C.byref(cfg),
+                                      _ptr(tables), tables.shape[0], _ptr(tidx) if tidx.size else None, splits,
+                                      C.byref(h)), "recoil_encode_adaptive")
+    return Blob(h)
+
+
 def encode_partitioned(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, partitions: int = 1,
                        alphabet: Optional[int] = None, freq: Optional[np.ndarray] = None) -> Blob:
     """The conventional baseline (Sec. 2.3): `partitions` independently coded sub-sequences
@@ -206,6 +227,15 @@ class Plan:
         check(_lib.recoil_decode(self._h, C.c_void_p(workspace.data_ptr()), C.c_void_p(out.data_ptr()),
                                  C.c_void_p(err.data_ptr()), _stream_handle(stream)), "recoil_decode")
 
+
+    def decode_adaptive(self, workspace, table_index, out, err, stream=None) -> None:
+        """recoil_decode_adaptive: table_index is a uint8 device tensor of N entries."""
+        if table_index.numel() < self.n_symbols or table_index.element_size() != 1:
+            raise ValueError("table_index must hold N bytes")
+        check(_lib.recoil_decode_adaptive(self._h, C.c_void_p(workspace.data_ptr()),
+                                          C.c_void_p(table_index.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          C.c_void_p(err.data_ptr()), _stream_handle(stream)),
+              "recoil_decode_adaptive")
 
     def decode_count_writes(self, workspace, out, counts, err, stream=None) -> None:
         """recoil_decode_count_writes: decode and add 1 to counts[i] (int32 device tensor

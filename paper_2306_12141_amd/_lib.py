@@ -49,6 +49,8 @@ recoil_last_error = _sig("recoil_last_error", [], C.c_char_p)
 recoil_version = _sig("recoil_version", [], C.c_char_p)
 recoil_quantize = _sig("recoil_quantize", [P, u32, u32, P])
 recoil_encode = _sig("recoil_encode", [P, u64, C.POINTER(Config), P, u32, C.POINTER(P)])
+recoil_encode_adaptive = _sig("recoil_encode_adaptive", [P, u64, C.POINTER(Config), P, u32, P, u32, C.POINTER(P)])
+recoil_decode_adaptive = _sig("recoil_decode_adaptive", [P, P, P, P, P, P])
 recoil_encode_partitioned = _sig("recoil_encode_partitioned", [P, u64, C.POINTER(Config), P, u32, C.POINTER(P)])
 recoil_combine_splits = _sig("recoil_combine_splits", [P, u32, C.POINTER(P)])
 recoil_blob_serialize = _sig("recoil_blob_serialize", [P, P, sz, C.POINTER(sz)])

@@ -63,6 +63,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         p.words = reinterpret_cast<const uint16_t *>(bp.ws + d.words_off);
         p.lut = nullptr;
         p.counts = nullptr;
+        p.tidx = nullptr;
+        p.tables = 1;
         p.meta = reinterpret_cast<const UnitMeta *>(bp.ws + d.meta_off);
         p.lanes = reinterpret_cast<const uint32_t *>(bp.ws + d.lanes_off);
         p.out = bp.out + d.out_off;

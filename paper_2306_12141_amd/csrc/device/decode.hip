@@ -46,17 +46,17 @@ using namespace dev;
 // SS: units per wave. W = 32 runs two units per wave (one per half-wave), or,
 // when the stream has no more units than the grid has waves, one unit per wave
 // with the upper half-wave switched off: then twice as many waves decode.
-template <int W, typename Sym, int K, int WAVES, int SS = 64 / W, bool COUNT = false>
+template <int W, typename Sym, int K, int WAVES, int SS = 64 / W, int VAR = kPlain>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET))) void decode_units(
     DecodeParams p) {
-    using D = PairDecoder<W, Sym, K, SS, COUNT>;
+    using D = PairDecoder<W, Sym, K, SS, VAR>;
     using L = Lds<0, K, WAVES>;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *lut = smem + L::TABLE;
     const uint32_t base = lds_addr(smem);
     {
         const uint4 *src = static_cast<const uint4 *>(p.lut);
-        const uint32_t chunks = ((uint32_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits) / 16;
+        const uint32_t chunks = (((uint32_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits) * p.tables) / 16;
         for (uint32_t i = threadIdx.x; i < chunks; i += 64 * WAVES) reinterpret_cast<uint4 *>(lut)[i] = src[i];
     }
     __syncthreads();
@@ -81,29 +81,29 @@ __global__ __launch_bounds__(256) void fill_symbol(Sym *out, uint64_t n, Sym v) 
 }
 
 template <int W, typename Sym, int K, int WAVES>
-size_t lds_bytes(uint32_t quant_bits) {
-    return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits);
+size_t lds_bytes(uint32_t quant_bits, uint32_t tables) {
+    return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits) * tables;
 }
 
-template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
-int units_occupancy(uint32_t quant_bits) {
+template <int W, typename Sym, int K, int WAVES, int SS, int VAR>
+int units_occupancy(uint32_t quant_bits, uint32_t tables) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS, COUNT>, 64 * WAVES,
-                                                     lds_bytes<W, Sym, K, WAVES>(quant_bits)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS, VAR>, 64 * WAVES,
+                                                     lds_bytes<W, Sym, K, WAVES>(quant_bits, tables)) != hipSuccess)
         return 0;
     return per_cu;
 }
 
 // Resident workgroups of the kernel with SS units per wave (0: does not fit).
-template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
+template <int W, typename Sym, int K, int WAVES, int SS, int VAR>
 uint32_t resident_blocks(const DecodeParams &p, const DecodeTuning &t) {
-    int per_cu = units_occupancy<W, Sym, K, WAVES, SS, COUNT>(p.quant_bits);
+    int per_cu = units_occupancy<W, Sym, K, WAVES, SS, VAR>(p.quant_bits, p.tables);
     if (per_cu < 1) return 0;
     if (t.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)t.blocks_per_cu);
     return (uint32_t)(device_cus() * per_cu);
 }
 
-template <int W, typename Sym, int K, int WAVES, int SS, bool COUNT>
+template <int W, typename Sym, int K, int WAVES, int SS, int VAR>
 hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resident, hipStream_t stream,
                      DecodeShape *shape) {
     DecodeParams q = p;
@@ -118,30 +118,30 @@ hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resi
         *shape = DecodeShape{blocks, (uint32_t)WAVES, q.run, q.runs, (uint32_t)SS};
         return hipSuccess;
     }
-    const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits);
-    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS, COUNT>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
+    const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits, p.tables);
+    hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS, VAR>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
     return hipGetLastError();
 }
 
-template <int W, typename Sym, int K, int WAVES, bool COUNT>
+template <int W, typename Sym, int K, int WAVES, int VAR>
 hipError_t launch_units(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     if constexpr (W == 32) {
         // One unit per wave when every run then has a wave of its own: the
         // pair kernel would leave half of those waves idle.
-        const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1, COUNT>(p, t);
+        const uint32_t rs = resident_blocks<32, Sym, K, WAVES, 1, VAR>(p, t);
         const uint64_t slots = (uint64_t)rs * WAVES;
         const uint32_t k = t.units_per_run && !p.partitioned ? std::min(t.units_per_run, std::max(p.units, 1u)) : 1u;
         const uint64_t runs = ((uint64_t)p.units + k - 1) / k;
-        if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1, COUNT>(p, t, rs, stream, shape);
+        if (rs > 0 && runs <= slots) return launch_ss<32, Sym, K, WAVES, 1, VAR>(p, t, rs, stream, shape);
     }
-    const uint32_t resident = resident_blocks<W, Sym, K, WAVES, 64 / W, COUNT>(p, t);
+    const uint32_t resident = resident_blocks<W, Sym, K, WAVES, 64 / W, VAR>(p, t);
     if (resident == 0) return hipErrorInvalidConfiguration;
-    return launch_ss<W, Sym, K, WAVES, 64 / W, COUNT>(p, t, resident, stream, shape);
+    return launch_ss<W, Sym, K, WAVES, 64 / W, VAR>(p, t, resident, stream, shape);
 }
 
 constexpr uint32_t kSimdsPerCu = 4;
 
-template <int W, typename Sym, bool COUNT>
+template <int W, typename Sym, int VAR>
 hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_t stream, DecodeShape *shape) {
     if (t.waves == 0) {
         // Automatic: 16 waves per workgroup; one when the launch has no more
@@ -153,20 +153,22 @@ hipError_t launch_shape(const DecodeParams &p, const DecodeTuning &t, hipStream_
         DecodeTuning u = t;
         u.waves = 16;
         DecodeShape s{};
-        const hipError_t e = launch_shape<W, Sym, COUNT>(p, u, stream, &s);
+        const hipError_t e = launch_shape<W, Sym, VAR>(p, u, stream, &s);
         if (e != hipSuccess) return e;
         const uint64_t pieces = s.units_per_wave ? (s.runs + s.units_per_wave - 1) / s.units_per_wave : 0;
         const uint64_t cus = (uint64_t)device_cus();
         if (pieces <= kSimdsPerCu * cus) u.waves = 1;
         else if (pieces < 16 * cus) u.waves = 8;
-        return launch_shape<W, Sym, COUNT>(p, u, stream, shape);
+        return launch_shape<W, Sym, VAR>(p, u, stream, shape);
     }
-    if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1, COUNT>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 1) return launch_units<W, Sym, 8, 1, COUNT>(p, t, stream, shape);
-    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16, COUNT>(p, t, stream, shape);
-    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8, COUNT>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8, COUNT>(p, t, stream, shape);
-    if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16, COUNT>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 1) return launch_units<W, Sym, 4, 1, VAR>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 16) return launch_units<W, Sym, 4, 16, VAR>(p, t, stream, shape);
+    if (t.chunk_groups == 4 && t.waves == 8) return launch_units<W, Sym, 4, 8, VAR>(p, t, stream, shape);
+    if constexpr (VAR != kAdaptive) {   // adaptive tables take the LDS of 8-group rings: K = 4 only
+        if (t.chunk_groups == 8 && t.waves == 1) return launch_units<W, Sym, 8, 1, VAR>(p, t, stream, shape);
+        if (t.chunk_groups == 8 && t.waves == 8) return launch_units<W, Sym, 8, 8, VAR>(p, t, stream, shape);
+        if (t.chunk_groups == 8 && t.waves == 16) return launch_units<W, Sym, 8, 16, VAR>(p, t, stream, shape);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -202,18 +204,25 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
     }
-    if (p.counts) {
-        // Checking launches: the same kernels, also counting every symbol store.
-        if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, true>(p, t, stream, shape);
-        if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, true>(p, t, stream, shape);
-        if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, true>(p, t, stream, shape);
-        if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, true>(p, t, stream, shape);
+    if (p.tidx) {
+        // Adaptive coding: per-symbol tables, uint8 symbols only.
+        if (p.counts || symbol_bytes != 1) return hipErrorInvalidValue;
+        if (lanes == 32) return launch_shape<32, uint8_t, kAdaptive>(p, t, stream, shape);
+        if (lanes == 64) return launch_shape<64, uint8_t, kAdaptive>(p, t, stream, shape);
         return hipErrorInvalidValue;
     }
-    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, false>(p, t, stream, shape);
-    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, false>(p, t, stream, shape);
-    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, false>(p, t, stream, shape);
-    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, false>(p, t, stream, shape);
+    if (p.counts) {
+        // Checking launches: the same kernels, also counting every symbol store.
+        if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, kCount>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, kCount>(p, t, stream, shape);
+        if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, kCount>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, kCount>(p, t, stream, shape);
+        return hipErrorInvalidValue;
+    }
+    if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, kPlain>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, kPlain>(p, t, stream, shape);
+    if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, kPlain>(p, t, stream, shape);
+    if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, kPlain>(p, t, stream, shape);
     return hipErrorInvalidValue;
 }
 

@@ -36,6 +36,8 @@ struct DecodeParams {
     void *out;                  // N symbols
     uint32_t *err;              // device error word
     uint32_t *counts;           // checking launches only: N per-symbol store counts (else NULL)
+    const uint8_t *tidx;        // adaptive coding: N per-symbol table indices (else NULL)
+    uint32_t tables;            // decode tables in lut (1 unless adaptive)
     uint64_t n_symbols;
     uint32_t units;
     uint32_t run;               // consecutive units decoded as one (Sec. 3.3): 1 uses every split point

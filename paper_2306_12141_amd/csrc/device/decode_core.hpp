@@ -72,6 +72,13 @@ struct Table<uint8_t> {
         x = __umul24(f, x >> n) + (e >> 20);
         return e;             // the low byte is the symbol
     }
+    // Adaptive coding: the symbol's own table t of the 2^n-entry tables laid end to end.
+    __device__ static inline uint32_t step_t(uint32_t lut, uint32_t &x, uint32_t n, uint32_t mask, uint32_t t) {
+        const Entry e = lds_ld<Entry>(lut + (((t << n) | (x & mask)) << 2));
+        const uint32_t f = (e >> 8) & 0xFFFu;
+        x = __umul24(f, x >> n) + (e >> 20);
+        return e;
+    }
 };
 
 template <>
@@ -145,13 +152,19 @@ __device__ inline T uni_load(const T *src) {
 // fit are kept in VGPR lanes and mostly reloaded outside the group loops).
 #define RECOIL_SGPR_BUDGET 64
 
-// COUNT: a checking build that also adds 1 to counts[i] for every store of symbol i.
-template <int W, typename Sym, int K, int SS = 64 / W, bool COUNT = false>
+// Kernel variants: kCount also adds 1 to counts[i] for every store of symbol i (a
+// checking launch); kAdaptive codes symbol i with decode table tidx[i] (adaptive
+// coding, uint8 symbols).
+constexpr int kPlain = 0, kCount = 1, kAdaptive = 2;
+
+template <int W, typename Sym, int K, int SS = 64 / W, int VAR = kPlain>
 struct PairDecoder {
     using G = Geo<W, K, SS>;
     using T = Table<Sym>;
     using Chunk = typename G::Chunk;
     static constexpr uint32_t S = G::S, C = G::C, R = G::R;
+    static constexpr bool COUNT = VAR == kCount, ADAPT = VAR == kAdaptive;
+    static_assert(!ADAPT || sizeof(Sym) == 1, "adaptive decoding reads the table index at the symbol's byte offset");
 
     const DecodeParams &p;
     uint32_t lut;          // LDS address of the decode table
@@ -178,6 +191,10 @@ struct PairDecoder {
     // address at which it wraps, and a mask that confines a read ballot to the
     // lane's own half-wave.
     uint32_t vb, vlim, lowmask;
+    // Adaptive coding: the table indices of this super-step's K groups and of the
+    // next one's (fetched a super-step ahead); tvalid: tcur holds this super-step's.
+    uint32_t tcur[K], tnxt[K];
+    bool tvalid = false;
     uint32_t x, rec, act, lim;
     uint32_t my_top, my_ghi, my_steps, lane_off;
     bool active;
@@ -347,10 +364,20 @@ struct PairDecoder {
         x = need ? ((x << 16) | w) : x;
     }
 
+    // This lane's table indices of the K groups from group top0 - k down (the bytes
+    // at its output offsets; only for groups inside the stream).
+    __device__ inline void load_tidx(uint32_t k, uint32_t (&dst)[K]) const {
+        const uint8_t *b = p.tidx + (uint64_t)(top0 - k) * W + lane_off;
+#pragma unroll
+        for (uint32_t g = 0; g < K; ++g) dst[g] = *(b - (int64_t)(g * W));
+    }
+
     template <uint32_t G_IDX>
     __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh) {
         read_step<G_IDX>(x < kL, a, e);
-        const uint32_t s = T::step(lut, x, n, mask);
+        uint32_t s;
+        if constexpr (ADAPT) s = T::step_t(lut, x, n, mask, tcur[G_IDX]);
+        else s = T::step(lut, x, n, mask);
         unsigned char *dst = outh + lane_off - G_IDX * W * sizeof(Sym);
         *reinterpret_cast<Sym *>(dst) = (Sym)s;
         if constexpr (COUNT) count_store((uint64_t)(dst - static_cast<unsigned char *>(p.out)) / sizeof(Sym));
@@ -369,7 +396,9 @@ struct PairDecoder {
         const uint32_t h = my_top - k;
         const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
-            const uint32_t s = T::step(lut, x, n, mask);
+            uint32_t s;
+            if constexpr (ADAPT) s = T::step_t(lut, x, n, mask, p.tidx[i]);
+            else s = T::step(lut, x, n, mask);
             if (h <= my_ghi) {
                 static_cast<Sym *>(p.out)[i] = (Sym)s;
                 if constexpr (COUNT) count_store(i);
@@ -391,8 +420,10 @@ struct PairDecoder {
         read_step<G_IDX>(x < lim, a, e);
         uint32_t lb = lut;
         asm volatile("" : "+s"(lb));   // the table base as a scalar operand of the address
-        const uint32_t s = T::step(lb, x, n, mask);
         const uint32_t h = my_top - k;
+        uint32_t s;
+        if constexpr (ADAPT) s = T::step_t(lb, x, n, mask, p.tidx[(uint64_t)h * W + coder]);
+        else s = T::step(lb, x, n, mask);
         if (h <= my_ghi) {
             static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
             if constexpr (COUNT) count_store((uint64_t)h * W + coder);
@@ -424,7 +455,13 @@ struct PairDecoder {
     // within the ring plus its mirror.) Returns false if a unit read past its
     // first word (corrupt split data).
     template <int MODE, uint32_t KK = K>
-    __device__ inline bool super_step(uint32_t k) {
+    __device__ inline bool super_step(uint32_t k, bool next_fast = false) {
+        if constexpr (ADAPT && MODE == kFast) {
+            // Table indices: this super-step's if not fetched ahead, and the next
+            // super-step's when it is also a fast one (its groups are then inside the stream).
+            if (!tvalid) load_tidx(k, tcur);
+            if (next_fast) load_tidx(k + K, tnxt);
+        }
         // Per lane: does this lane's unit fetch? (Uniform within each half-wave.)
         const bool need = (MODE != kPred || my_steps > k) && vfq > 0 && vres < 2 * (int32_t)C;
         uint32_t a = ua[0], e = S == 2 ? vb : 0u;
@@ -457,6 +494,11 @@ struct PairDecoder {
         } else {
             vres -= (int32_t)((e - vb) >> 1);
             vb = e >= vlim ? e - 2 * R : e;
+        }
+        if constexpr (ADAPT && MODE == kFast) {
+#pragma unroll
+            for (uint32_t g = 0; g < K; ++g) tcur[g] = tnxt[g];
+            tvalid = next_fast;
         }
         return __ballot(vres < 0) == 0;   // read below the first word: corrupt split data
     }
@@ -511,6 +553,7 @@ struct PairDecoder {
         // over into the sub-sequence below.
         bool run_on = !p.partitioned && k <= kmin && top_min + 1 >= kend;
         run_on = run_on && __ballot(vres + vfq * (int32_t)C < (int32_t)((kend - k) * W)) == 0;
+        tvalid = false;
         if (run_on) {
             for (; ok && k < kmax; k += K) {
                 if (8 * k > thr) {
@@ -518,7 +561,7 @@ struct PairDecoder {
                     thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
                     set_priority(level);
                 }
-                ok = super_step<kFast>(k);
+                ok = super_step<kFast>(k, k + K < kmax);
             }
         } else {
             for (; ok && k + K <= kmin; k += K) {
@@ -527,7 +570,7 @@ struct PairDecoder {
                     thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
                     set_priority(level);
                 }
-                ok = super_step<kFast>(k);
+                ok = super_step<kFast>(k, k + 2 * K <= kmin);
             }
             for (; ok && k < kmax; k += K) ok = super_step<kPred>(k);
         }

@@ -22,7 +22,11 @@ constexpr uint64_t kMaxGroupDiff = 65535;
 struct BlobData {
     uint32_t lanes = 0, quant_bits = 0, symbol_bytes = 0, alphabet = 0;
     uint64_t n_symbols = 0;
-    std::vector<uint32_t> freq;          // f[s], sums to 2^n
+    std::vector<uint32_t> freq;          // f[s], sums to 2^n; adaptive: tables x A, table t at t A
+    // Adaptive coding (Sec. 3.1): symbol i was coded with table tidx[i] of `tables`;
+    // the index array is side information the decoder is given again.
+    bool adaptive = false;
+    uint32_t tables = 1;
     std::vector<uint32_t> final_states;  // W
     // B words, written forward, read backward; shared between a blob and the
     // blobs combined from it (the bitstream is the same, only split points differ).

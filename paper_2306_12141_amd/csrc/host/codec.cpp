@@ -280,11 +280,13 @@ private:
     std::vector<Cand> cand_;
 };
 
+// tidx: adaptive coding (symbol i with table tidx[i]), or NULL for the one table.
 template <typename Sym>
-void encode_stream(const Sym *sym, BlobData &b, uint32_t threads) {
-    const uint32_t W = b.lanes, n = b.quant_bits;
-    std::vector<uint32_t> F(b.alphabet + 1, 0);
-    for (uint32_t s = 0; s < b.alphabet; ++s) F[s + 1] = F[s] + b.freq[s];
+void encode_stream(const Sym *sym, BlobData &b, uint32_t threads, const uint8_t *tidx = nullptr) {
+    const uint32_t W = b.lanes, n = b.quant_bits, A = b.alphabet;
+    std::vector<uint32_t> F((size_t)b.tables * (A + 1), 0);   // table t's cumulative counts at t (A + 1)
+    for (uint32_t t = 0; t < b.tables; ++t)
+        for (uint32_t s = 0; s < A; ++s) F[(size_t)t * (A + 1) + s + 1] = F[(size_t)t * (A + 1) + s] + b.freq[(size_t)t * A + s];
     SplitChooser chooser(b, threads);
     const bool want_splits = threads > 1;
     uint32_t x[64];
@@ -296,7 +298,8 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads) {
     uint32_t j = 0;
     for (uint64_t i = 0; i < b.n_symbols; ++i) {
         const uint32_t s = sym[i];
-        const uint32_t fs = b.freq[s];
+        const uint32_t t = tidx ? tidx[i] : 0u;
+        const uint32_t fs = b.freq[(size_t)t * A + s];
         uint32_t xs = x[j];
         if ((uint64_t)xs >= ((uint64_t)fs << shift)) {
             // Emit the low word first, then shift (Eq. 3).
@@ -305,7 +308,7 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads) {
             if (want_splits)
                 chooser.event(words.size() - 1, (int64_t)i - (int64_t)W, xs);
         }
-        x[j] = ((xs / fs) << n) + F[s] + (xs % fs);     // Eq. 1
+        x[j] = ((xs / fs) << n) + F[(size_t)t * (A + 1) + s] + (xs % fs);     // Eq. 1
         if (++j == W) j = 0;
     }
     if (want_splits) chooser.finish();
@@ -324,9 +327,13 @@ bool pack_sections(BlobData &b) {
     b.table_bits.clear();
     b.meta_bits.clear();
     {
+        // One series per table, back to back in one bit stream.
         BitSink s(b.table_bits);
-        if (!put_series(s, b.alphabet, 5, false, [&](uint64_t k) { return (int64_t)b.freq[k]; }))
-            return false;
+        for (uint32_t t = 0; t < b.tables; ++t) {
+            const uint64_t base = (uint64_t)t * b.alphabet;
+            if (!put_series(s, b.alphabet, 5, false, [&](uint64_t k) { return (int64_t)b.freq[base + k]; }))
+                return false;
+        }
         s.flush();
     }
     if (b.partitioned()) {
@@ -453,6 +460,40 @@ recoil_status encode(const void *symbols, uint64_t N, const recoil_config *cfg, 
     return RECOIL_OK;
 }
 
+recoil_status encode_adaptive(const void *symbols, uint64_t N, const recoil_config *cfg, const uint32_t *freqs,
+                              uint32_t tables, const uint8_t *tidx, uint32_t threads, recoil_blob **out) {
+    if (!out) return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: out is NULL");
+    *out = nullptr;
+    if (!cfg || (N > 0 && (!symbols || !tidx)) || !freqs || threads < 1 || tables < 1 || tables > 256)
+        return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: bad arguments");
+    const uint32_t W = cfg->lanes, n = cfg->quant_bits, sb = cfg->symbol_bytes, A = cfg->alphabet;
+    if (W < 1 || W > 64 || n < 1 || n > 16 || (sb != 1 && sb != 2) || A < 1 || A > (sb == 1 ? 256u : 65536u))
+        return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: configuration out of range");
+    auto b = std::make_shared<BlobData>();
+    b->lanes = W; b->quant_bits = n; b->symbol_bytes = sb; b->alphabet = A; b->n_symbols = N;
+    b->adaptive = true;
+    b->tables = tables;
+    b->freq.assign(freqs, freqs + (size_t)tables * A);
+    for (uint32_t t = 0; t < tables; ++t) {
+        uint64_t tot = 0;
+        for (uint32_t s = 0; s < A; ++s) tot += b->freq[(size_t)t * A + s];
+        if (tot != (1ull << n)) return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: a table does not sum to 2^n");
+    }
+    for (uint64_t i = 0; i < N; ++i) {
+        const uint32_t s = sb == 1 ? ((const uint8_t *)symbols)[i] : ((const uint16_t *)symbols)[i];
+        if (s >= A || tidx[i] >= tables) return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: symbol or table index out of range");
+        if (!b->freq[(size_t)tidx[i] * A + s]) return fail(RECOIL_ERR_INFEASIBLE, "encode_adaptive: symbol has zero frequency in its table");
+    }
+    if (sb == 1) encode_stream((const uint8_t *)symbols, *b, threads, tidx);
+    else encode_stream((const uint16_t *)symbols, *b, threads, tidx);
+    if (!pack_sections(*b)) return fail(RECOIL_ERR_INFEASIBLE, "encode_adaptive: metadata does not fit its series");
+    auto *h = new (std::nothrow) recoil_blob();
+    if (!h) return fail(RECOIL_ERR_INVALID_ARG, "encode_adaptive: out of memory");
+    h->data = std::move(b);
+    *out = h;
+    return RECOIL_OK;
+}
+
 namespace {
 
 // One sub-sequence of the conventional baseline: W interleaved coders from state L
@@ -519,6 +560,7 @@ std::shared_ptr<BlobData> combine_data(const BlobData &a, uint32_t target) {
     b->lanes = a.lanes; b->quant_bits = a.quant_bits; b->symbol_bytes = a.symbol_bytes;
     b->alphabet = a.alphabet; b->n_symbols = a.n_symbols;
     b->freq = a.freq; b->final_states = a.final_states; b->words_buf = a.words_buf;
+    b->adaptive = a.adaptive; b->tables = a.tables;
     const uint64_t W = a.lanes;
     const size_t kept = M / step;
     b->sp_next.reserve(kept); b->sp_anchor.reserve(kept);
@@ -556,7 +598,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     if (cap < total) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "serialize: destination too small");
     std::vector<uint8_t> h;
     h.reserve(48);
-    h.push_back('R'); h.push_back('C'); h.push_back(b.partitioned() ? 'P' : 'L'); h.push_back('1');
+    h.push_back('R'); h.push_back('C'); h.push_back(b.partitioned() ? 'P' : b.adaptive ? 'A' : 'L'); h.push_back('1');
     put_u(h, 1, 2);
     h.push_back((uint8_t)b.lanes); h.push_back((uint8_t)b.quant_bits); h.push_back((uint8_t)b.symbol_bytes);
     h.push_back((uint8_t)kLowerBits); h.push_back((uint8_t)kWordBits); h.push_back(0);
@@ -566,7 +608,7 @@ recoil_status serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *
     put_u(h, b.splits(), 4);
     put_u(h, b.table_bits.size(), 4);
     put_u(h, b.meta_bits.size(), 4);
-    put_u(h, b.part_size, 4);
+    put_u(h, b.partitioned() ? b.part_size : b.adaptive ? b.tables : 0, 4);
     uint8_t *p = (uint8_t *)dst;
     std::memcpy(p, h.data(), 48);
     p += 48;
@@ -658,9 +700,13 @@ recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
         if (get_u(c + 4, 2) != 1) return fail(RECOIL_ERR_CORRUPT, "container: unknown version");
         return deserialize_partitioned(c, len, out);
     }
-    if (len < 48 || std::memcmp(c, "RCL1", 4) != 0) return fail(RECOIL_ERR_CORRUPT, "container: bad magic");
+    const bool adaptive = len >= 48 && std::memcmp(c, "RCA1", 4) == 0;
+    if (len < 48 || (!adaptive && std::memcmp(c, "RCL1", 4) != 0)) return fail(RECOIL_ERR_CORRUPT, "container: bad magic");
     if (get_u(c + 4, 2) != 1) return fail(RECOIL_ERR_CORRUPT, "container: unknown version");
     auto b = std::make_shared<BlobData>();
+    b->adaptive = adaptive;
+    b->tables = adaptive ? (uint32_t)get_u(c + 44, 4) : 1u;
+    if (b->tables < 1 || b->tables > 256) return fail(RECOIL_ERR_CORRUPT, "container: table count out of range");
     b->lanes = c[6]; b->quant_bits = c[7]; b->symbol_bytes = c[8];
     const uint32_t lbits = c[9], wbits = c[10];
     b->alphabet = (uint32_t)get_u(c + 12, 4);
@@ -669,7 +715,7 @@ recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
     const uint64_t M = get_u(c + 32, 4);
     const uint64_t tbytes = get_u(c + 36, 4), mbytes = get_u(c + 40, 4);
     const uint32_t W = b->lanes, n = b->quant_bits, sb = b->symbol_bytes, A = b->alphabet;
-    if (c[11] != 0 || get_u(c + 44, 4) != 0) return fail(RECOIL_ERR_CORRUPT, "container: reserved bytes set");
+    if (c[11] != 0 || (!adaptive && get_u(c + 44, 4) != 0)) return fail(RECOIL_ERR_CORRUPT, "container: reserved bytes set");
     if (W < 1 || W > 64 || n < 1 || n > 16 || (sb != 1 && sb != 2) || A < 1 || A > (sb == 1 ? 256u : 65536u))
         return fail(RECOIL_ERR_CORRUPT, "container: parameters out of range");
     if (lbits != kLowerBits || wbits != kWordBits) return fail(RECOIL_ERR_UNSUPPORTED, "container: only L = 2^16, b = 16 supported");
@@ -683,16 +729,19 @@ recoil_status deserialize(const void *src, size_t len, recoil_blob **out) {
     const uint8_t *q = c + 48;
     {
         BitSource s(q, tbytes);
-        std::vector<int64_t> fv;
-        if (!get_series(s, A, 5, false, fv) || cdiv(s.pos(), 8) != tbytes) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
-        uint64_t tot = 0;
-        b->freq.resize(A);
-        for (uint32_t k = 0; k < A; ++k) {
-            if (fv[k] > (int64_t)(1u << n)) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
-            b->freq[k] = (uint32_t)fv[k];
-            tot += (uint64_t)fv[k];
+        b->freq.resize((size_t)b->tables * A);
+        for (uint32_t t = 0; t < b->tables; ++t) {
+            std::vector<int64_t> fv;
+            if (!get_series(s, A, 5, false, fv)) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
+            uint64_t tot = 0;
+            for (uint32_t k = 0; k < A; ++k) {
+                if (fv[k] > (int64_t)(1u << n)) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
+                b->freq[(size_t)t * A + k] = (uint32_t)fv[k];
+                tot += (uint64_t)fv[k];
+            }
+            if (tot != (1ull << n)) return fail(RECOIL_ERR_CORRUPT, "container: table does not sum to 2^n");
         }
-        if (tot != (1ull << n)) return fail(RECOIL_ERR_CORRUPT, "container: table does not sum to 2^n");
+        if (cdiv(s.pos(), 8) != tbytes) return fail(RECOIL_ERR_CORRUPT, "container: bad table");
     }
     q += tbytes;
     b->final_states.resize(W);
@@ -793,6 +842,12 @@ recoil_status recoil_quantize(const uint64_t *counts, uint32_t alphabet, uint32_
 recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                             const uint32_t *freq, uint32_t n_splits, recoil_blob **out) {
     return recoil::encode(symbols, n_symbols, cfg, freq, n_splits, out);
+}
+
+recoil_status recoil_encode_adaptive(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
+                                     const uint32_t *freqs, uint32_t tables, const uint8_t *table_index,
+                                     uint32_t n_splits, recoil_blob **out) {
+    return recoil::encode_adaptive(symbols, n_symbols, cfg, freqs, tables, table_index, n_splits, out);
 }
 
 recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,

@@ -32,12 +32,14 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     if (b.n_symbols >= (1ull << 32) || b.n_words() + kChunkPadWords >= (1ull << 31))
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
+    if (b.adaptive && (b.symbol_bytes != 1 || ((uint64_t)b.tables << (n + 2)) > kMaxAdaptiveTableBytes))
+        return fail(RECOIL_ERR_UNSUPPORTED, "plan: adaptive decoding needs uint8 symbols and tables x 2^n x 4 <= 64 KiB");
     pl.blob = bp;
     // Default launch shape: waves per workgroup chosen at launch (16, or 1 for
     // launches with few runs), 8-group super-steps when the table is small enough
     // for two 16-wave workgroups per CU (uint8 symbols), 4-group otherwise.
     pl.tuning.waves = 0;
-    pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
+    pl.tuning.chunk_groups = b.symbol_bytes == 1 && !b.adaptive ? 8 : 4;
     pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
     pl.meta.resize(M);
@@ -159,15 +161,17 @@ void build_table(const BlobData &b, PlanData &pl) {
     uint32_t present = 0, only = 0;
     for (uint32_t s = 0; s < b.alphabet; ++s)
         if (b.freq[s]) { ++present; only = s; }
-    pl.single_symbol = present == 1;
+    pl.single_symbol = present == 1 && !b.adaptive;
     pl.fill_symbol = only;
     const size_t esz = b.symbol_bytes == 1 ? 4 : 8;
-    pl.lut.assign((size_t)slots * esz, 0);
+    // Adaptive coding: the tables' decode tables end to end, table t at slot t 2^n.
+    pl.lut.assign((size_t)slots * esz * b.tables, 0);
+    for (uint32_t t = 0; t < b.tables; ++t) {
     uint32_t F = 0;
     for (uint32_t s = 0; s < b.alphabet; ++s) {
-        const uint32_t f = b.freq[s];
+        const uint32_t f = b.freq[(size_t)t * b.alphabet + s];
         for (uint32_t r = 0; r < f; ++r) {
-            const uint32_t slot = F + r;
+            const uint32_t slot = t * slots + F + r;
             if (b.symbol_bytes == 1) {
                 const uint32_t e = s | ((f & 0xFFFu) << 8) | (r << 20);
                 std::memcpy(&pl.lut[(size_t)slot * 4], &e, 4);
@@ -178,6 +182,7 @@ void build_table(const BlobData &b, PlanData &pl) {
             }
         }
         F += f;
+    }
     }
 }
 
@@ -273,6 +278,8 @@ recoil::DecodeParams decode_params(const recoil::PlanData &pl, const void *d_ws,
     p.fill_symbol = pl.fill_symbol;
     p.single_symbol = pl.single_symbol ? 1u : 0u;
     p.partitioned = b.partitioned() ? 1u : 0u;
+    p.tables = b.tables;
+    p.tidx = nullptr;
     return p;
 }
 
@@ -286,9 +293,27 @@ recoil_status recoil_decode(const recoil_plan *plan, const void *d_ws, void *d_o
     if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
         return fail(RECOIL_ERR_ALIGNMENT, "decode: output must be 16-byte and workspace 256-byte aligned");
     const PlanData &pl = plan->d;
+    if (pl.blob->adaptive && pl.blob->n_symbols)
+        return fail(RECOIL_ERR_INVALID_ARG, "decode: an adaptive stream needs its table index (recoil_decode_adaptive)");
     const DecodeParams p = decode_params(pl, d_ws, d_out, d_error);
     hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+recoil_status recoil_decode_adaptive(const recoil_plan *plan, const void *d_ws, const uint8_t *d_table_index,
+                                     void *d_out, uint32_t *d_error, hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws || !d_error || ((!d_out || !d_table_index) && plan->d.blob->n_symbols))
+        return fail(RECOIL_ERR_INVALID_ARG, "decode_adaptive: bad arguments");
+    if (!plan->d.blob->adaptive) return fail(RECOIL_ERR_INVALID_ARG, "decode_adaptive: not an adaptive stream");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(RECOIL_ERR_ALIGNMENT, "decode_adaptive: output must be 16-byte and workspace 256-byte aligned");
+    const PlanData &pl = plan->d;
+    DecodeParams p = decode_params(pl, d_ws, d_out, d_error);
+    p.tidx = d_table_index;
+    hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_adaptive: ") + hipGetErrorString(e));
     return RECOIL_OK;
 }
 
@@ -302,6 +327,7 @@ recoil_status recoil_decode_count_writes(const recoil_plan *plan, const void *d_
         return fail(RECOIL_ERR_ALIGNMENT, "decode_count_writes: misaligned buffer");
     const PlanData &pl = plan->d;
     if (pl.single_symbol) return fail(RECOIL_ERR_UNSUPPORTED, "decode_count_writes: single-symbol stream (no decode kernel)");
+    if (pl.blob->adaptive) return fail(RECOIL_ERR_UNSUPPORTED, "decode_count_writes: adaptive stream");
     DecodeParams p = decode_params(pl, d_ws, d_out, d_error);
     p.counts = d_counts;
     hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
@@ -349,6 +375,7 @@ recoil_status recoil_plan_autotune(recoil_plan *plan, void *d_ws, void *d_out, u
         return fail(RECOIL_ERR_INVALID_ARG, "plan_autotune: bad arguments");
     PlanData &pl = plan->d;
     const BlobData &b = *pl.blob;
+    if (b.adaptive) return fail(RECOIL_ERR_UNSUPPORTED, "plan_autotune: adaptive streams keep the default shape");
     auto report = [&](const DecodeTuning &t, float ms) {
         if (best_out) *best_out = recoil_tuning{t.waves, t.chunk_groups, 1, t.blocks_per_cu, t.units_per_run};
         if (best_ms) *best_ms = ms;

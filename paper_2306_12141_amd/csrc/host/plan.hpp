@@ -23,6 +23,8 @@ struct PlanData {
 };
 
 constexpr size_t kWsAlign = 256;
+// Adaptive coding: the decode tables of all tables must fit LDS beside the rings.
+constexpr uint64_t kMaxAdaptiveTableBytes = 65536;
 inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
 // Unpack split metadata and build the decode table; fills the single-stream layout.

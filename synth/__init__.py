@@ -278,3 +278,28 @@ def log_uniform_int(seed: int, i: int, lo: int, hi: int) -> int:
         return lo
     v = int(_log_uniform(uniform01(seed, i), lo, hi + 1))
     return max(lo, min(hi, v))
+
+
+def adaptive_stream(seed: int, n: int, tables: int = 16, alphabet: int = 64, block: int = 256):
+    """Adaptive-coding stand-in for hyperprior-modelled image latents (Sec. 5.1).
+
+    `tables` discrete Laplace distributions centred at alphabet / 2 with scales
+    spread geometrically from 0.5 to 16; a per-symbol table index that is
+    piecewise constant over blocks of `block` symbols (the seeded block value)
+    with a seeded per-symbol jitter of -1 / 0 / +1 (clipped), so that lanes of
+    one symbol group use different tables; each symbol drawn from its own
+    table's distribution. Returns (pmfs [tables x alphabet], index [n] uint8,
+    symbols [n] uint8).
+    """
+    scales = 0.5 * (32.0 ** (np.arange(tables) / max(tables - 1, 1)))
+    pmfs = np.stack([laplace_pmf(alphabet, alphabet / 2, float(sc)) for sc in scales])
+    nb = -(-n // block)
+    base = (splitmix64(seed, 0, nb) % np.uint64(tables)).astype(np.int64)
+    jitter = (splitmix64(seed ^ 0x717, 0, n) % np.uint64(3)).astype(np.int64) - 1
+    tidx = np.clip(np.repeat(base, block)[:n] + jitter, 0, tables - 1).astype(np.uint8)
+    symbols = np.zeros(n, dtype=np.uint8)
+    for t in range(tables):
+        where = np.nonzero(tidx == t)[0]
+        if len(where):
+            symbols[where] = draw_symbols(pmfs[t], (seed << 8) + t, len(where), np.uint8)
+    return pmfs, tidx, symbols

@@ -432,3 +432,41 @@ def test_partitioned_streams(rc, orc, W, N, P, dt):
     assert int(err.item()) == 0
     assert np.array_equal(plan.symbols_of(out), s)
     assert int(counts.min().item()) == 1 and int(counts.max().item()) == 1
+
+
+@pytest.mark.parametrize("W,n,T,A,nbits,M,run", [(32, 2_000_003, 16, 64, 9, 512, 0), (64, 1 << 21, 8, 64, 10, 300, 0),
+                                                (32, 1 << 21, 16, 64, 9, 4096, 1), (32, 1 << 22, 4, 256, 12, 20000, 0),
+                                                (64, 100_001, 2, 128, 11, 1000, 3), (32, 70, 16, 64, 9, 3, 0)])
+def test_adaptive_streams(rc, orc, W, n, T, A, nbits, M, run):
+    """Adaptive coding (Sec. 3.1): every symbol decoded with the table its index names.
+    Containers byte-identical to the oracle's; outputs equal the input symbols, also
+    combined; a wrong index gives a different output."""
+    pmfs, tidx, s = synth.adaptive_stream(700 + T + W, n, T, A)
+    tabs = np.stack([orc.quantize((pmf * (1 << 30)).astype(np.uint64) + 1, nbits) for pmf in pmfs])
+    blob = rc.encode_adaptive(s, tabs, tidx, lanes=W, quant_bits=nbits, splits=M, alphabet=A)
+    assert blob.to_bytes() == orc.encode_adaptive(s, orc.params(lanes=W, quant_bits=nbits, alphabet=A), tabs, tidx,
+                                                  M).container()
+    d_tidx = torch.from_numpy(tidx).to("cuda")
+    for b in (blob, blob.combine(max(1, M // 7))):
+        plan = rc.Plan(b)
+        if run:
+            plan.set_tuning(chunk_groups=4, units_per_run=run)
+        ws = plan.allocate_workspace()
+        plan.upload(ws)
+        for poison in (0xA5, 0x5A):
+            out = plan.allocate_output()
+            out.fill_(poison)
+            err = torch.zeros(1, dtype=torch.int32, device="cuda")
+            plan.decode_adaptive(ws, d_tidx, out, err)
+            torch.cuda.synchronize()
+            assert int(err.item()) == 0
+            assert np.array_equal(plan.symbols_of(out), s), f"splits {b.splits}"
+    if T > 1:
+        wrong = tidx.copy()
+        wrong[::3] = (wrong[::3] + 1) % T
+        out.fill_(0)
+        plan.decode_adaptive(ws, torch.from_numpy(wrong).to("cuda"), out, err)
+        torch.cuda.synchronize()
+        assert not np.array_equal(plan.symbols_of(out), s)
+    with pytest.raises(rc.RecoilError):
+        plan.decode(ws, out, err)                   # the index is required

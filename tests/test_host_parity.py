@@ -236,3 +236,33 @@ def test_partitioned_corruption_rejected(rc, orc):
             bad[hdr:hdr + 4] = (5).to_bytes(4, "little")
         with pytest.raises(rc.RecoilError):
             rc.Blob.from_bytes(bytes(bad))
+
+
+def _adaptive_case(orc, seed, n, T, A, nbits):
+    pmfs, tidx, s = synth.adaptive_stream(seed, n, T, A)
+    tabs = np.stack([orc.quantize((pmf * (1 << 30)).astype(np.uint64) + 1, nbits) for pmf in pmfs])
+    return tabs, tidx, s
+
+
+@pytest.mark.parametrize("W,n,T,A,M", [(32, 200_001, 16, 64, 97), (64, 65_536, 4, 256, 33), (32, 5000, 1, 64, 1)])
+def test_adaptive_byte_identical(rc, orc, W, n, T, A, M):
+    """Adaptive coding: librecoil's container equals the oracle's, deserialises to the
+    same bytes, combines like the oracle's, and plans T decode tables."""
+    nbits = 9 if T == 16 else 11
+    tabs, tidx, s = _adaptive_case(orc, 300 + W + T, n, T, A, nbits)
+    p = orc.params(lanes=W, quant_bits=nbits, alphabet=A)
+    ref = orc.encode_adaptive(s, p, tabs, tidx, M).container()
+    blob = rc.encode_adaptive(s, tabs, tidx, lanes=W, quant_bits=nbits, splits=M, alphabet=A)
+    assert blob.to_bytes() == ref and ref[:4] == b"RCA1"
+    assert rc.Blob.from_bytes(ref).to_bytes() == ref
+    assert blob.combine(7).to_bytes() == orc.combine(ref, 7)
+    assert len(rc.Plan(blob).units()) == blob.splits
+    with pytest.raises(rc.RecoilError):       # a table index beyond the tables
+        rc.encode_adaptive(s, tabs, np.full_like(tidx, T), lanes=W, quant_bits=nbits, splits=M, alphabet=A)
+
+
+def test_adaptive_plan_limits(rc, orc):
+    """The GPU decodes adaptive uint8 streams whose tables fit 64 KiB of LDS."""
+    tabs, tidx, s = _adaptive_case(orc, 9, 10_000, 32, 64, 10)       # 32 x 1024 x 4 B = 128 KiB
+    with pytest.raises(rc.RecoilError):
+        rc.Plan(rc.encode_adaptive(s, tabs, tidx, lanes=32, quant_bits=10, splits=4, alphabet=64))

@@ -555,3 +555,96 @@ def test_partitioned_overhead_per_part(orc):
         per.append((len(orc.encode_partitioned(s, p, P)) - base) / (P - 1))
     assert all(85 <= v <= 115 for v in per), per
     assert abs(per[0] - per[1]) / per[1] < 0.1
+
+
+# ---------------------------------------------------------------------------
+# Adaptive coding (Sec. 3.1, third advantage of storing symbol indices)
+# ---------------------------------------------------------------------------
+
+def test_adaptive_one_table_is_static(orc, c0):
+    """One table and an all-zero index: the same words, final states and metadata
+    as the static container; only the magic and the table count differ."""
+    _, s, p, _, _ = c0
+    f = _fmt_table(orc, s, p)
+    static = orc.encode(s, p, 64, freq=f).container()
+    adapt = orc.encode_adaptive(s, p, f[None, :], np.zeros(len(s), np.uint8), 64).container()
+    assert adapt[:4] == b"RCA1" and static[:4] == b"RCL1"
+    assert adapt[4:44] == static[4:44] and int.from_bytes(adapt[44:48], "little") == 1
+    assert adapt[48:] == static[48:]
+
+
+def test_adaptive_two_table_code_length(orc):
+    """Table 0: 256 symbols of f = 1 at n = 8 (each symbol is x -> 256 x + s, 8 bits);
+    table 1: f = 128 for symbols 0 and 1 (x -> 2 x - (x mod 128) + F, 1 bit). With the
+    index choosing per symbol, the code length is 8 bits per table-0 symbol plus 1
+    bit per table-1 symbol, within log2(e) 2^(n-1) / L per step."""
+    N, W = 4096, 1
+    tidx = (synth.splitmix64(31, 0, N) % np.uint64(2)).astype(np.uint8)
+    s = _rng_symbols(32, N, 256)
+    s[tidx == 1] &= 1
+    t0 = np.ones(256, np.uint32)
+    t1 = np.zeros(256, np.uint32)
+    t1[:2] = 128
+    p = orc.params(lanes=W, quant_bits=8)
+    enc = orc.encode_adaptive(s, p, np.stack([t0, t1]), tidx, 1)
+    c = enc.container()
+    B = int.from_bytes(c[24:32], "little")
+    table_bytes = int.from_bytes(c[36:40], "little")
+    final = np.frombuffer(c[48 + table_bytes: 48 + table_bytes + 4 * W], dtype="<u4")
+    total = 16 * B + sum(math.log2(int(x)) for x in final) - 16 * W
+    ideal = 8 * int((tidx == 0).sum()) + int((tidx == 1).sum())
+    assert abs(total - ideal) <= N * 1.4427 * 128 / 2.0 ** 16
+    d = orc.Decoder(c)
+    d.set_table_index(tidx)
+    assert np.array_equal(d.serial(), s)
+
+
+def test_adaptive_round_trip_threads_combine_and_wrong_index(orc):
+    """Per-symbol tables chosen from a seeded index: serial and per-split decoding,
+    combining, and a decoder given a different index does not reproduce the input."""
+    N, T, A = 150_001, 6, 64
+    tidx = (synth.splitmix64(7, 0, N) % np.uint64(T)).astype(np.uint8)
+    tabs = np.stack([orc.quantize((synth.laplace_pmf(A, A / 2, 0.7 + 3 * t) * 1e6 + 1).astype(np.uint64), 10)
+                     for t in range(T)])
+    s = np.zeros(N, np.uint8)
+    for t in range(T):
+        m = tidx == t
+        s[m] = synth.draw_symbols(synth.laplace_pmf(A, A / 2, 0.7 + 3 * t), 40 + t, int(m.sum()), np.uint8)
+    for W in (32, 64):
+        p = orc.params(lanes=W, quant_bits=10, alphabet=A)
+        c = orc.encode_adaptive(s, p, tabs, tidx, 100).container()
+        d = orc.Decoder(c)
+        with pytest.raises(orc.OracleError):
+            d.serial()                                     # the index is required
+        d.set_table_index(tidx)
+        assert d.threads == 100
+        assert np.array_equal(d.serial(), s) and np.array_equal(d.all(aligned=True, workers=3), s)
+        for target in (7, 1):
+            dc = orc.Decoder(orc.combine(c, target))
+            dc.set_table_index(tidx)
+            assert np.array_equal(dc.all(), s)
+        wrong = tidx.copy()
+        wrong[::5] = (wrong[::5] + 1) % T
+        dw = orc.Decoder(c)
+        dw.set_table_index(wrong)
+        try:
+            assert not np.array_equal(dw.serial(), s)
+        except orc.OracleError:
+            pass
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_adaptive_brute_force_tiny(orc, lanes):
+    """L = 2^4, b = 4, n = 3, two tables over 3 symbols: every sequence of length 6
+    with two index patterns, encoded with 1..3 decode units, decodes exactly."""
+    p = orc.params(lanes=lanes, quant_bits=3, alphabet=3, l_bits=4, b_bits=4)
+    tabs = np.array([[1, 2, 5], [6, 1, 1]], dtype=np.uint32)
+    for seq in itertools.product(range(3), repeat=6):
+        s = np.array(seq, dtype=np.uint8)
+        for pat in (np.array([0, 1, 1, 0, 1, 0], np.uint8), np.array([1, 1, 1, 0, 0, 0], np.uint8)):
+            for threads in (1, 2, 3):
+                c = orc.encode_adaptive(s, p, tabs, pat, threads).container()
+                d = orc.Decoder(c)
+                d.set_table_index(pat)
+                assert np.array_equal(d.serial(), s)
+                assert np.array_equal(d.all(fill=255), s) and np.array_equal(d.all(aligned=True, fill=255), s)
