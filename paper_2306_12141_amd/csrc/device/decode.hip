@@ -47,7 +47,7 @@ using namespace dev;
 // when the stream has no more units than the grid has waves, one unit per wave
 // with the upper half-wave switched off: then twice as many waves decode.
 template <int W, typename Sym, int K, int WAVES, int SS = 64 / W, int VAR = kPlain>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET))) void decode_units(
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET), amdgpu_waves_per_eu(8))) void decode_units(
     DecodeParams p) {
     using D = PairDecoder<W, Sym, K, SS, VAR>;
     using L = Lds<0, K, WAVES>;

@@ -191,10 +191,12 @@ struct PairDecoder {
     // address at which it wraps, and a mask that confines a read ballot to the
     // lane's own half-wave.
     uint32_t vb, vlim, lowmask;
-    // Adaptive coding: the table indices of this super-step's K groups and of the
-    // next one's (fetched a super-step ahead); tvalid: tcur holds this super-step's.
-    uint32_t tcur[K], tnxt[K];
-    bool tvalid = false;
+    // Adaptive coding: the table indices of the fast super-steps k and k + K (fetched
+    // a super-step ahead; tready: tcur already holds super-step k's). A predicated or
+    // synchronisation super-step fetches its own into tcur at its start (those run
+    // outside the fast loops, so the registers are free then).
+    uint32_t tcur[K], tn1[K];
+    uint32_t tready = 0;
     uint32_t x, rec, act, lim;
     uint32_t my_top, my_ghi, my_steps, lane_off;
     bool active;
@@ -372,6 +374,18 @@ struct PairDecoder {
         for (uint32_t g = 0; g < K; ++g) dst[g] = *(b - (int64_t)(g * W));
     }
 
+    // The same for KK groups of a predicated or synchronisation super-step, where a
+    // lane's group may lie outside its unit or the stream: those lanes load nothing.
+    template <uint32_t KK>
+    __device__ inline void load_tidx_checked(uint32_t k) {
+#pragma unroll
+        for (uint32_t g = 0; g < KK; ++g) {
+            const uint32_t kk = k + g;
+            const uint64_t i = (uint64_t)(my_top - kk) * W + coder;
+            tcur[g] = (kk <= my_top && i < p.n_symbols) ? (uint32_t)p.tidx[i] : 0u;
+        }
+    }
+
     template <uint32_t G_IDX>
     __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh) {
         read_step<G_IDX>(x < kL, a, e);
@@ -397,7 +411,7 @@ struct PairDecoder {
         const uint64_t i = (uint64_t)h * W + coder;
         if (live && active && i < p.n_symbols) {
             uint32_t s;
-            if constexpr (ADAPT) s = T::step_t(lut, x, n, mask, p.tidx[i]);
+            if constexpr (ADAPT) s = T::step_t(lut, x, n, mask, tcur[G_IDX]);
             else s = T::step(lut, x, n, mask);
             if (h <= my_ghi) {
                 static_cast<Sym *>(p.out)[i] = (Sym)s;
@@ -422,7 +436,7 @@ struct PairDecoder {
         asm volatile("" : "+s"(lb));   // the table base as a scalar operand of the address
         const uint32_t h = my_top - k;
         uint32_t s;
-        if constexpr (ADAPT) s = T::step_t(lb, x, n, mask, p.tidx[(uint64_t)h * W + coder]);
+        if constexpr (ADAPT) s = T::step_t(lb, x, n, mask, tcur[G_IDX]);
         else s = T::step(lb, x, n, mask);
         if (h <= my_ghi) {
             static_cast<Sym *>(p.out)[(uint64_t)h * W + coder] = (Sym)s;
@@ -454,13 +468,16 @@ struct PairDecoder {
     // most C words, so a unit keeps at least C words resident, and reads stay
     // within the ring plus its mirror.) Returns false if a unit read past its
     // first word (corrupt split data).
+    // fend: fast super-steps of the current loop are those at k' with k' + K <= fend.
     template <int MODE, uint32_t KK = K>
-    __device__ inline bool super_step(uint32_t k, bool next_fast = false) {
+    __device__ inline bool super_step(uint32_t k, uint32_t fend = 0) {
         if constexpr (ADAPT && MODE == kFast) {
-            // Table indices: this super-step's if not fetched ahead, and the next
-            // super-step's when it is also a fast one (its groups are then inside the stream).
-            if (!tvalid) load_tidx(k, tcur);
-            if (next_fast) load_tidx(k + K, tnxt);
+            // Table indices: this super-step's unless fetched ahead, and the next
+            // one's when it is also fast (its groups are then inside the stream).
+            if (!tready) load_tidx(k, tcur);
+            if (k + 2 * K <= fend) load_tidx(k + K, tn1);
+        } else if constexpr (ADAPT) {
+            load_tidx_checked<KK>(k);
         }
         // Per lane: does this lane's unit fetch? (Uniform within each half-wave.)
         const bool need = (MODE != kPred || my_steps > k) && vfq > 0 && vres < 2 * (int32_t)C;
@@ -497,8 +514,8 @@ struct PairDecoder {
         }
         if constexpr (ADAPT && MODE == kFast) {
 #pragma unroll
-            for (uint32_t g = 0; g < K; ++g) tcur[g] = tnxt[g];
-            tvalid = next_fast;
+            for (uint32_t g = 0; g < K; ++g) tcur[g] = tn1[g];
+            tready = k + 2 * K <= fend ? 1u : 0u;
         }
         return __ballot(vres < 0) == 0;   // read below the first word: corrupt split data
     }
@@ -553,7 +570,7 @@ struct PairDecoder {
         // over into the sub-sequence below.
         bool run_on = !p.partitioned && k <= kmin && top_min + 1 >= kend;
         run_on = run_on && __ballot(vres + vfq * (int32_t)C < (int32_t)((kend - k) * W)) == 0;
-        tvalid = false;
+        tready = 0;
         if (run_on) {
             for (; ok && k < kmax; k += K) {
                 if (8 * k > thr) {
@@ -561,7 +578,7 @@ struct PairDecoder {
                     thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
                     set_priority(level);
                 }
-                ok = super_step<kFast>(k, k + K < kmax);
+                ok = super_step<kFast>(k, kend);
             }
         } else {
             for (; ok && k + K <= kmin; k += K) {
@@ -570,7 +587,7 @@ struct PairDecoder {
                     thr = level ? thr + (prio_cut(level + 1) - prio_cut(level)) * q : 0xFFFFFFFFu;
                     set_priority(level);
                 }
-                ok = super_step<kFast>(k, k + 2 * K <= kmin);
+                ok = super_step<kFast>(k, kmin);
             }
             for (; ok && k < kmax; k += K) ok = super_step<kPred>(k);
         }
