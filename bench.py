@@ -406,6 +406,56 @@ def run_combined(args, base, torch, np, rc):
     return rows
 
 
+def run_unpack(args, base, torch, np, rc):
+    """Split metadata unpacked on the device (packed plans, Sec. 4.3 format) against
+    the host planner, on one stream: host time to create the plan (the host
+    planner unpacks every split point's lane records; a packed plan copies the
+    packed section), metadata bytes uploaded, and the unpack kernel's duration,
+    for every split point and combined to fewer units (the host planner gets the
+    combined blob made beforehand). Each packed plan's records are compared word
+    for word with the host planner's, and its decode checked exact."""
+    blob, s = base["blob"], base["symbols"]
+    M = blob.splits
+    rows = []
+    for target in (0, M // 4, 64, 1):
+        hb = blob.combine(target) if 0 < target < M else blob
+        t0 = time.perf_counter()
+        hb2 = blob.combine(target) if 0 < target < M else blob
+        combine_s = time.perf_counter() - t0
+        del hb2
+        host_s = _median_time(lambda: rc.Plan(hb), reps=5)
+        packed_s = _median_time(lambda: rc.Plan(blob, packed_target=target), reps=5)
+        host, packed = rc.Plan(hb), rc.Plan(blob, packed_target=target)
+        ws_h = host.allocate_workspace()
+        host.upload(ws_h)
+        ws_p = packed.allocate_workspace()
+        ws_p.fill_(0xC3)
+        packed.upload(ws_p)
+        torch.cuda.synchronize()
+        rp, lp = packed.device_records(ws_p)
+        rh, lh = host.device_records(ws_h)
+        same = bool(np.array_equal(rp, rh) and np.array_equal(lp, lh))
+        del ws_h
+        mean_ms, med_ms = _time_launches(lambda: packed.unpack(ws_p), 50, 5, torch)
+        out = packed.allocate_output()
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        packed.decode(ws_p, out, err)
+        torch.cuda.synchronize()
+        exact = check_exact(packed, out, s, err, np) and same
+        U = packed.layout().unit_count
+        rows.append({"units": U, "records_equal_host": same, "exact": exact,
+                     "host_plan_ms": round(host_s * 1e3, 3), "packed_plan_ms": round(packed_s * 1e3, 3),
+                     "combine_ms": round(combine_s * 1e3, 3) if hb is not blob else 0.0,
+                     "host_metadata_bytes": host.metadata_device_bytes,
+                     "packed_metadata_bytes": packed.metadata_device_bytes,
+                     "unpack_kernel_ms_mean": round(mean_ms, 5), "unpack_kernel_ms_median": round(med_ms, 5)})
+        log(f"unpack: {U} units, host plan {host_s * 1e3:.2f} ms vs packed {packed_s * 1e3:.2f} ms + kernel "
+            f"{med_ms * 1e3:.1f} us, metadata {host.metadata_device_bytes} vs {packed.metadata_device_bytes} B, "
+            f"exact={exact}")
+        del ws_p, out, err, host, packed, hb
+    return rows
+
+
 def run_conventional(args, base, torch, np, rc):
     """The conventional partitioning baseline (Sec. 2.3) on the same stream: P
     independently coded sub-sequences, decoded by the same kernels (no synchronisation).
@@ -870,6 +920,7 @@ def main():
         w32 = other if other_lanes == 32 else base
         extras["combined_w32"] = run_combined(args, w32, torch, np, rc)
         extras["conventional_w32"] = run_conventional(args, w32, torch, np, rc)
+        extras["device_unpack_w32"] = run_unpack(args, w32, torch, np, rc)
         extras["adaptive"] = run_adaptive(args, torch, np, rc, synth)
         del other, w32
         extras["c0"] = run_c0(args, torch, np, rc, synth)

@@ -243,8 +243,45 @@ recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, siz
  * Errors: INVALID_ARG, ALIGNMENT, HIP. */
 recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_workspace, size_t bytes,
                                  hipStream_t stream);
-/* Size in bytes of the split metadata as uploaded (part of device_bytes). */
+/* Size in bytes of the split metadata as uploaded (part of device_bytes): unit
+ * and lane records, or for a packed plan the packed section, the block offsets
+ * and the final states. */
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan);
+
+/*
+ * Device-side metadata unpacking (Sec. 4.3 format). Like recoil_plan_create, but
+ * the per-unit and per-lane records are not built on the host: recoil_plan_upload
+ * copies the packed metadata section as the container stores it (two signed
+ * series, then per split point W 16-bit states and a group-difference series),
+ * the bit offset of each split point's block (u32) and the W final states, and
+ * queues a kernel on the same stream that writes the records into the workspace
+ * before any decode queued after it on that stream.
+ * target_units: decode units of the plan; every ceil(M / target)-th split point is
+ * kept (the combining of Sec. 3.3, records identical to those of the combined
+ * blob; 0 or >= M keeps all M units).
+ * recoil_plan_units reports the count only (the records exist on the device);
+ * recoil_plan_get_layout gives where they are.
+ * Errors: INVALID_ARG, UNSUPPORTED (as recoil_plan_create; conventional
+ * partitioned streams; a metadata section of 2^32 bits or more).
+ */
+recoil_status recoil_plan_create_packed(const recoil_blob *blob, uint32_t target_units, recoil_plan **out,
+                                        size_t *device_bytes);
+/* Queue only the unpack kernel of a packed plan on `stream`, reading the packed
+ * section, block offsets and final states that recoil_plan_upload already placed
+ * in d_workspace (which must not have been modified since) and rewriting the
+ * unit and lane records. Errors: INVALID_ARG (not a packed plan), ALIGNMENT, HIP. */
+recoil_status recoil_plan_unpack(const recoil_plan *plan, void *d_workspace, hipStream_t stream);
+
+/* Byte offsets of a plan's workspace sections (from the workspace base): words,
+ * decode table, unit records (unit_count x 4 u32: next, top, ghi, glo, as
+ * recoil_plan_units describes) and lane words (unit_count x lanes_per_unit u32:
+ * a split point's lane state in bits 0..15 and its activation step in bits
+ * 16..31, or the 32-bit final state for the last unit); total = device_bytes. */
+typedef struct {
+    size_t words, table, units, lanes, total;
+    uint32_t unit_count, lanes_per_unit, packed;
+} recoil_plan_layout;
+recoil_status recoil_plan_get_layout(const recoil_plan *plan, recoil_plan_layout *out);
 /* Launch shape used by recoil_decode for this plan (default: waves 0, i.e. 16
  * per workgroup or 1 for decodes with few runs; K = 8 groups per super-step for
  * uint8 tables, 4 for uint16; units_per_run 0). pairs_per_wave is ignored.
@@ -318,7 +355,8 @@ recoil_status recoil_decode_count_writes(const recoil_plan *plan, const void *d_
  * the anchor), highest group stored (ghi), lowest group decoded and stored (glo).
  * records = NULL: only *count (the number of units) is set.
  * cap: capacity of records in units (4 words each).
- * Errors: INVALID_ARG, BUFFER_TOO_SMALL (cap below the number of units).
+ * Errors: INVALID_ARG, BUFFER_TOO_SMALL (cap below the number of units),
+ * UNSUPPORTED (records requested of a packed plan: they exist on the device only).
  */
 recoil_status recoil_plan_units(const recoil_plan *plan, uint32_t *records, uint32_t cap, uint32_t *count);
 

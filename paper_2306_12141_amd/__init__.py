@@ -156,12 +156,20 @@ def _stream_handle(stream) -> C.c_void_p:
 
 
 class Plan:
-    """GPU decode plan of one blob: device workspace layout plus decode launch."""
+    """GPU decode plan of one blob: device workspace layout plus decode launch.
 
-    def __init__(self, blob: Blob):
+    packed_target=None: records unpacked on the host (recoil_plan_create). An
+    integer: recoil_plan_create_packed, the device unpacks the packed metadata
+    section at upload, keeping every ceil(M / target)-th split point (0: all)."""
+
+    def __init__(self, blob: Blob, packed_target: Optional[int] = None):
         self._h = C.c_void_p()
         n = C.c_size_t()
-        check(_lib.recoil_plan_create(blob.handle, C.byref(self._h), C.byref(n)), "recoil_plan_create")
+        if packed_target is None:
+            check(_lib.recoil_plan_create(blob.handle, C.byref(self._h), C.byref(n)), "recoil_plan_create")
+        else:
+            check(_lib.recoil_plan_create_packed(blob.handle, int(packed_target), C.byref(self._h), C.byref(n)),
+                  "recoil_plan_create_packed")
         self.device_bytes = n.value
         info = blob.info
         self.n_symbols = info.n_symbols
@@ -210,6 +218,11 @@ class Plan:
         check(_lib.recoil_plan_upload(self._h, C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                       _stream_handle(stream)), "recoil_plan_upload")
 
+    def unpack(self, workspace, stream=None) -> None:
+        """Packed plans: queue the device unpack again on an uploaded workspace."""
+        check(_lib.recoil_plan_unpack(self._h, C.c_void_p(workspace.data_ptr()), _stream_handle(stream)),
+              "recoil_plan_unpack")
+
     def allocate_output(self, device="cuda"):
         """A byte tensor of N * symbol_bytes bytes (torch has few uint16 kernels)."""
         import torch
@@ -246,6 +259,21 @@ class Plan:
                                               C.c_void_p(out.data_ptr()), C.c_void_p(counts.data_ptr()),
                                               C.c_void_p(err.data_ptr()), _stream_handle(stream)),
               "recoil_decode_count_writes")
+
+    def layout(self) -> _lib.PlanLayout:
+        """Byte offsets of the workspace sections, unit count and lanes per unit."""
+        lay = _lib.PlanLayout()
+        check(_lib.recoil_plan_get_layout(self._h, C.byref(lay)), "recoil_plan_get_layout")
+        return lay
+
+    def device_records(self, workspace):
+        """(units x 4 records, units x W lane words) read back from an uploaded workspace."""
+        lay = self.layout()
+        U, W = lay.unit_count, lay.lanes_per_unit
+        ws = workspace[lay.units: lay.lanes + 4 * U * W].cpu().numpy()
+        rec = ws[: 16 * U].view(np.uint32).reshape(U, 4)
+        lanes = ws[lay.lanes - lay.units:].view(np.uint32).reshape(U, W)
+        return rec.copy(), lanes.copy()
 
     def units(self) -> np.ndarray:
         """Per-unit records (units x 4: next, top, ghi, glo) as the kernels read them."""

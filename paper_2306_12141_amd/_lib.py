@@ -64,6 +64,16 @@ recoil_plan_free = _sig("recoil_plan_free", [P], None)
 recoil_decode = _sig("recoil_decode", [P, P, P, P, P])
 recoil_decode_count_writes = _sig("recoil_decode_count_writes", [P, P, P, P, P, P])
 recoil_plan_units = _sig("recoil_plan_units", [P, P, u32, C.POINTER(u32)])
+recoil_plan_create_packed = _sig("recoil_plan_create_packed", [P, u32, C.POINTER(P), C.POINTER(sz)])
+recoil_plan_unpack = _sig("recoil_plan_unpack", [P, P, P])
+
+
+class PlanLayout(C.Structure):
+    _fields_ = [("words", sz), ("table", sz), ("units", sz), ("lanes", sz), ("total", sz),
+                ("unit_count", u32), ("lanes_per_unit", u32), ("packed", u32)]
+
+
+recoil_plan_get_layout = _sig("recoil_plan_get_layout", [P, C.POINTER(PlanLayout)])
 
 
 class RecoilError(RuntimeError):

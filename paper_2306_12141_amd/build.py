@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "librecoil.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["host/codec.cpp", "host/plan.cpp", "host/batch.cpp", "host/server.cpp", "host/staging.cpp"]
-DEVICE_SOURCES = ["device/decode.hip", "device/batch.hip"]
+DEVICE_SOURCES = ["device/decode.hip", "device/batch.hip", "device/unpack.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall"]

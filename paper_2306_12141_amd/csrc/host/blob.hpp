@@ -43,9 +43,13 @@ struct BlobData {
     uint64_t part_size = 0;
     std::vector<uint64_t> part_start;
     std::vector<uint32_t> part_final;
-    // Packed sections, computed once.
+    // Packed sections, computed once; for the metadata also the bit position of
+    // the group series and of each split point's block (so a device can unpack the
+    // blocks in parallel).
     std::vector<uint8_t> table_bits;
     std::vector<uint8_t> meta_bits;
+    uint64_t x_series_bit = 0;
+    std::vector<uint64_t> block_bit;     // M-1
 
     bool partitioned() const { return part_size != 0; }
     uint32_t splits() const { return partitioned() ? (uint32_t)part_start.size() : (uint32_t)sp_next.size() + 1; }

@@ -44,6 +44,7 @@ public:
         n_ = 0;
         acc_ = 0;
     }
+    uint64_t bit_pos() const { return 8ull * out_.size() + n_; }
 
 private:
     std::vector<uint8_t> &out_;
@@ -326,6 +327,8 @@ recoil_status fail(recoil_status s, const std::string &msg) {
 bool pack_sections(BlobData &b) {
     b.table_bits.clear();
     b.meta_bits.clear();
+    b.x_series_bit = 0;
+    b.block_bit.clear();
     {
         // One series per table, back to back in one bit stream.
         BitSink s(b.table_bits);
@@ -357,11 +360,14 @@ bool pack_sections(BlobData &b) {
             return (int64_t)b.sp_next[k] - (int64_t)((k + 1) * Eb);
         }))
         return false;
+    b.x_series_bit = s.bit_pos();
     if (!put_series(s, M - 1, 5, true, [&](uint64_t k) {
             return (int64_t)(b.sp_anchor[k] + 1) - (int64_t)((k + 1) * Eg);   // 1-based group ids
         }))
         return false;
+    b.block_bit.assign(M - 1, 0);
     for (uint64_t k = 0; k + 1 < M; ++k) {
+        b.block_bit[k] = s.bit_pos();
         for (uint64_t j = 0; j < W; ++j) s.put(b.sp_state[k * W + j], 16);
         if (!put_series(s, W, 4, false, [&](uint64_t j) { return (int64_t)b.sp_gdiff[k * W + j]; }))
             return false;

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "../device/unpack.hpp"
 
 namespace recoil {
 
@@ -23,9 +24,8 @@ inline size_t align_up(size_t v) { return ws_align(v); }
 // top .. glo and stores ghi .. glo, where ghi is the group of its own
 // synchronisation completion point (all lanes switched on) and glo is one
 // above the previous unit's.
-recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
-    const BlobData &b = *bp;
-    const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
+recoil_status check_gpu_limits(const BlobData &b) {
+    const uint32_t W = b.lanes, n = b.quant_bits;
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
     // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
     if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
@@ -34,7 +34,15 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
     if (b.adaptive && (b.symbol_bytes != 1 || ((uint64_t)b.tables << (n + 2)) > kMaxAdaptiveTableBytes))
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: adaptive decoding needs uint8 symbols and tables x 2^n x 4 <= 64 KiB");
+    return RECOIL_OK;
+}
+
+recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
+    const BlobData &b = *bp;
+    const uint32_t W = b.lanes, M = b.splits();
+    if (recoil_status st = check_gpu_limits(b)) return st;
     pl.blob = bp;
+    pl.units = M;
     // Default launch shape: waves per workgroup chosen at launch (16, or 1 for
     // launches with few runs), 8-group super-steps when the table is small enough
     // for two 16-wave workgroups per CU (uint8 symbols), 4-group otherwise.
@@ -98,16 +106,13 @@ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return b ? (a + b - 1) / b : 
 recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, uint32_t target, PlanData &pl,
                                    uint64_t *packed_bytes) {
     const BlobData &b = *bp;
-    const uint32_t W = b.lanes, n = b.quant_bits, M = b.splits();
+    const uint32_t W = b.lanes, M = b.splits();
     if (b.partitioned()) return fail(RECOIL_ERR_UNSUPPORTED, "combine: sub-sequences cannot be merged");
-    if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
-    // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
-    if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
-    if (b.n_symbols >= (1ull << 32) || b.n_words() + kChunkPadWords >= (1ull << 31))
-        return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
+    if (recoil_status st = check_gpu_limits(b)) return st;
     const uint32_t step = (uint32_t)ceil_div(M, std::min(std::max(target, 1u), M));
     const uint32_t Mc = (M - 1) / step + 1;
     pl.blob = bp;
+    pl.units = Mc;
     pl.tuning.waves = 0;
     pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
     pl.tuning.blocks_per_cu = 0;
@@ -199,11 +204,66 @@ recoil_status build_plan(const std::shared_ptr<const BlobData> &bp, PlanData &pl
     return RECOIL_OK;
 }
 
+recoil_status build_plan_packed(const std::shared_ptr<const BlobData> &bp, uint32_t target, PlanData &pl) {
+    const BlobData &b = *bp;
+    if (b.partitioned()) return fail(RECOIL_ERR_UNSUPPORTED, "plan_create_packed: sub-sequence records are not packed");
+    if (recoil_status st = check_gpu_limits(b)) return st;
+    const uint32_t M = b.splits(), W = b.lanes;
+    if (b.block_bit.size() + 1 != M || 8ull * b.meta_bits.size() >= (1ull << 32))
+        return fail(RECOIL_ERR_UNSUPPORTED, "plan_create_packed: metadata section above 2^32 bits");
+    pl.blob = bp;
+    pl.packed = true;
+    pl.step = (uint32_t)ceil_div(M, target == 0 ? M : std::min(target, M));
+    pl.units = (M - 1) / pl.step + 1;
+    pl.tuning.waves = 0;
+    pl.tuning.chunk_groups = b.symbol_bytes == 1 && !b.adaptive ? 8 : 4;
+    pl.tuning.blocks_per_cu = 0;
+    pl.packed_bits.assign(b.meta_bits.size() + 8, 0);
+    std::copy(b.meta_bits.begin(), b.meta_bits.end(), pl.packed_bits.begin());
+    pl.block_bit.assign(b.block_bit.begin(), b.block_bit.end());
+    build_table(b, pl);
+    size_t off = 0;
+    pl.off_words = off;  off += words_section_bytes(b.n_words());
+    pl.off_lut = off;    off = align_up(off + pl.lut.size());
+    pl.off_meta = off;   off = align_up(off + (size_t)pl.units * sizeof(UnitMeta));
+    pl.off_lanes = off;  off = align_up(off + (size_t)pl.units * W * 4);
+    pl.off_bits = off;   off = align_up(off + pl.packed_bits.size());
+    pl.off_blocks = off; off = align_up(off + pl.block_bit.size() * 4);
+    pl.off_final = off;  off = align_up(off + (size_t)W * 4);
+    pl.total = off;
+    return RECOIL_OK;
+}
+
 }  // namespace recoil
 
 struct recoil_plan {
     recoil::PlanData d;
 };
+
+namespace {
+
+// The unpack kernel of a packed plan, reading the sections already in the workspace.
+hipError_t enqueue_unpack(const recoil::PlanData &pl, char *base, hipStream_t stream) {
+    using namespace recoil;
+    const BlobData &b = *pl.blob;
+    UnpackParams u{};
+    u.bits = reinterpret_cast<const uint8_t *>(base + pl.off_bits);
+    u.block_bit = reinterpret_cast<const uint32_t *>(base + pl.off_blocks);
+    u.final_states = reinterpret_cast<const uint32_t *>(base + pl.off_final);
+    u.meta = reinterpret_cast<UnitMeta *>(base + pl.off_meta);
+    u.lanes = reinterpret_cast<uint32_t *>(base + pl.off_lanes);
+    u.words = b.n_words();
+    u.groups = b.groups();
+    u.splits = b.splits();
+    u.eb = (u.words + u.splits - 1) / u.splits;
+    u.eg = (u.groups + u.splits - 1) / u.splits;
+    u.step = pl.step;
+    u.units = pl.units;
+    u.lanes_per_unit = b.lanes;
+    return launch_unpack(u, stream);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -220,9 +280,34 @@ recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, siz
     return RECOIL_OK;
 }
 
+recoil_status recoil_plan_create_packed(const recoil_blob *blob, uint32_t target_units, recoil_plan **out,
+                                        size_t *device_bytes) {
+    using namespace recoil;
+    if (!blob || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_create_packed: bad arguments");
+    *out = nullptr;
+    auto *p = new (std::nothrow) recoil_plan();
+    if (!p) return fail(RECOIL_ERR_INVALID_ARG, "plan_create_packed: out of memory");
+    recoil_status st = build_plan_packed(blob->data, target_units, p->d);
+    if (st) { delete p; return st; }
+    if (device_bytes) *device_bytes = p->d.total;
+    *out = p;
+    return RECOIL_OK;
+}
+
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan) {
     if (!plan) return 0;
-    return plan->d.meta.size() * sizeof(recoil::UnitMeta) + plan->d.lanes.size() * 4;
+    const recoil::PlanData &pl = plan->d;
+    if (pl.packed) return pl.blob->meta_bits.size() + pl.block_bit.size() * 4 + (size_t)pl.blob->lanes * 4;
+    return pl.meta.size() * sizeof(recoil::UnitMeta) + pl.lanes.size() * 4;
+}
+
+recoil_status recoil_plan_get_layout(const recoil_plan *plan, recoil_plan_layout *out) {
+    using namespace recoil;
+    if (!plan || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_get_layout: bad arguments");
+    const PlanData &pl = plan->d;
+    *out = recoil_plan_layout{pl.off_words, pl.off_lut, pl.off_meta, pl.off_lanes, pl.total, pl.units,
+                              pl.blob->lanes, pl.packed ? 1u : 0u};
+    return RECOIL_OK;
 }
 
 recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t bytes, hipStream_t stream) {
@@ -236,9 +321,29 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t byt
     hipError_t e = hipSuccess;
     if (b.n_words()) e = stage_h2d(base + pl.off_words, b.words(), 2 * b.n_words(), stream);
     if (e == hipSuccess) e = stage_h2d(base + pl.off_lut, pl.lut.data(), pl.lut.size(), stream);
-    if (e == hipSuccess) e = stage_h2d(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), stream);
-    if (e == hipSuccess) e = stage_h2d(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, stream);
+    if (pl.packed) {
+        // The packed section, block offsets and final states, then the unpacker
+        // writes the unit and lane records on the same stream.
+        if (e == hipSuccess) e = stage_h2d(base + pl.off_bits, pl.packed_bits.data(), pl.packed_bits.size(), stream);
+        if (e == hipSuccess && !pl.block_bit.empty())
+            e = stage_h2d(base + pl.off_blocks, pl.block_bit.data(), pl.block_bit.size() * 4, stream);
+        if (e == hipSuccess) e = stage_h2d(base + pl.off_final, b.final_states.data(), (size_t)b.lanes * 4, stream);
+        if (e == hipSuccess) e = enqueue_unpack(pl, base, stream);
+    } else {
+        if (e == hipSuccess) e = stage_h2d(base + pl.off_meta, pl.meta.data(), pl.meta.size() * sizeof(UnitMeta), stream);
+        if (e == hipSuccess) e = stage_h2d(base + pl.off_lanes, pl.lanes.data(), pl.lanes.size() * 4, stream);
+    }
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_upload: ") + hipGetErrorString(e));
+    return RECOIL_OK;
+}
+
+recoil_status recoil_plan_unpack(const recoil_plan *plan, void *d_ws, hipStream_t stream) {
+    using namespace recoil;
+    if (!plan || !d_ws) return fail(RECOIL_ERR_INVALID_ARG, "plan_unpack: bad arguments");
+    if (!plan->d.packed) return fail(RECOIL_ERR_INVALID_ARG, "plan_unpack: not a packed plan");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(RECOIL_ERR_ALIGNMENT, "plan_unpack: workspace not 256-byte aligned");
+    hipError_t e = enqueue_unpack(plan->d, static_cast<char *>(d_ws), stream);
+    if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_unpack: ") + hipGetErrorString(e));
     return RECOIL_OK;
 }
 
@@ -271,7 +376,7 @@ recoil::DecodeParams decode_params(const recoil::PlanData &pl, const void *d_ws,
     p.out = d_out;
     p.err = d_error;
     p.n_symbols = b.n_symbols;
-    p.units = b.splits();
+    p.units = pl.units;
     p.run = 1;
     p.runs = p.units;
     p.quant_bits = b.quant_bits;
@@ -339,8 +444,9 @@ recoil_status recoil_plan_units(const recoil_plan *plan, uint32_t *records, uint
     using namespace recoil;
     if (!plan) return fail(RECOIL_ERR_INVALID_ARG, "plan_units: NULL plan");
     const std::vector<UnitMeta> &m = plan->d.meta;
-    if (count) *count = (uint32_t)m.size();
+    if (count) *count = plan->d.units;
     if (!records) return RECOIL_OK;
+    if (plan->d.packed) return fail(RECOIL_ERR_UNSUPPORTED, "plan_units: a packed plan's records exist on the device only");
     if (cap < m.size()) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "plan_units: records too small");
     for (size_t u = 0; u < m.size(); ++u) {
         records[4 * u + 0] = m[u].next;
@@ -385,7 +491,7 @@ recoil_status recoil_plan_autotune(recoil_plan *plan, void *d_ws, void *d_out, u
     (void)hipGetDevice(&dev);
     (void)hipGetDeviceProperties(&prop, dev);
     const std::string key = std::string(prop.gcnArchName) + "/" + std::to_string(b.n_symbols) + "/" +
-                            std::to_string(b.splits()) + "/" + std::to_string(b.lanes) + "/" +
+                            std::to_string(pl.units) + "/" + std::to_string(b.lanes) + "/" +
                             std::to_string(b.symbol_bytes) + "/" + std::to_string(b.quant_bits);
     {
         std::lock_guard<std::mutex> lk(g_plan_tune_mu);

@@ -18,8 +18,16 @@ struct PlanData {
     DecodeTuning tuning;                 // launch shape for recoil_decode
     bool single_symbol = false;
     uint32_t fill_symbol = 0;
+    uint32_t units = 0;                  // decode units (meta.size() unless packed)
+    // Packed plans: the records are unpacked on the device from the stream's packed
+    // metadata section (kept split points (u+1) step, Sec. 3.3); meta and lanes stay empty.
+    bool packed = false;
+    uint32_t step = 1;
+    std::vector<uint8_t> packed_bits;    // the section + 8 zero bytes (the unpacker reads 5-byte windows)
+    std::vector<uint32_t> block_bit;     // M - 1 block bit offsets
     // Workspace layout of a single-stream plan (byte offsets from the workspace base).
     size_t off_words = 0, off_lut = 0, off_meta = 0, off_lanes = 0, total = 0;
+    size_t off_bits = 0, off_blocks = 0, off_final = 0;   // packed plans
 };
 
 constexpr size_t kWsAlign = 256;
@@ -29,6 +37,12 @@ inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAli
 
 // Unpack split metadata and build the decode table; fills the single-stream layout.
 recoil_status build_plan(const std::shared_ptr<const BlobData> &blob, PlanData &plan);
+// The same without unpacking: the decode table and the layout of a plan whose
+// records the device unpacks from the packed section, keeping every step-th
+// split point for ceil(M / target) units (target 0 or >= M: all).
+recoil_status build_plan_packed(const std::shared_ptr<const BlobData> &blob, uint32_t target, PlanData &plan);
+// GPU limits on a stream (lanes, n, sizes, adaptive tables); RECOIL_OK if decodable.
+recoil_status check_gpu_limits(const BlobData &blob);
 // The two halves of build_plan: per-unit and per-lane records only (checks the
 // GPU limits and sets the default tuning), and the decode table only.
 recoil_status build_units(const std::shared_ptr<const BlobData> &blob, PlanData &plan);

@@ -46,3 +46,62 @@ def parse_partitioned(c: bytes) -> dict:
     ends = np.append(starts[1:], B)
     return dict(lanes=lanes, N=N, B=B, P=P, S=S, table=c[48:48 + table_bytes], starts=starts,
                 final=rec[:, 1:], words=words, part_words=[words[a:b] for a, b in zip(starts, ends)])
+
+
+class BitReader:
+    """MSB-first reader of a packed section."""
+
+    def __init__(self, data: bytes):
+        self.s = bits(data)
+        self.pos = 0
+
+    def get(self, w: int) -> int:
+        v = int(self.s[self.pos:self.pos + w], 2)
+        self.pos += w
+        return v
+
+    def series(self, count: int, field: int, signed: bool) -> list:
+        w = self.get(field) + 1
+        out = []
+        for _ in range(count):
+            neg = self.get(1) if signed else 0
+            m = self.get(w)
+            out.append(-m if neg else m)
+        return out
+
+
+def unit_records(c: bytes, target: int = 0):
+    """Per-unit records (next, top, ghi, glo) and lane words that a decoder of the
+    container combined to `target` units starts from, read straight from the
+    packed metadata section: offset and group series, then per split point W
+    16-bit states and a group-difference series (Sec. 4.3 layout in
+    include/recoil.h). Every ceil(M / target)-th split point is kept (0: all)."""
+    h = parse(c)
+    W, M, B, N = h["lanes"], h["M"], h["B"], h["N"]
+    G = -(-N // W)
+    r = BitReader(h["meta"])
+    o = r.series(M - 1, 5, True) if M > 1 else []
+    x = r.series(M - 1, 5, True) if M > 1 else []
+    states, diffs = [], []
+    for _ in range(M - 1):
+        states.append([r.get(16) for _ in range(W)])
+        diffs.append(r.series(W, 4, False))
+    eb, eg = -(-B // M), -(-G // M)
+    step = -(-M // (M if target == 0 else min(target, M)))
+    units = (M - 1) // step + 1
+    rec = np.zeros((units, 4), dtype=np.uint32)
+    lanes = np.zeros((units, W), dtype=np.uint32)
+    prev_sync = None
+    for u in range(units):
+        glo = 0 if u == 0 else prev_sync + 1
+        if u + 1 == units:
+            rec[u] = (B, max(G - 1, 0), max(G - 1, 0), glo)
+            lanes[u] = h["final"]
+            continue
+        k = (u + 1) * step - 1
+        top = (k + 1) * eg + x[k] - 1
+        ghi = top - max(diffs[k])
+        rec[u] = ((k + 1) * eb + o[k], top, ghi, glo)
+        lanes[u] = [s | (d << 16) for s, d in zip(states[k], diffs[k])]
+        prev_sync = ghi
+    return rec, lanes
