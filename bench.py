@@ -13,7 +13,9 @@ The same line also carries (each bit-exact against the input symbols):
       the same stream coded by the conventional partitioning baseline (Sec. 2.3) at
       65536 / 16384 / 256 sub-sequences against Recoil at the same parallelism,
       adaptive coding (16 per-symbol tables) against one static table on the same
-      symbols, the small Laplace stream, and the host-to-device upload;
+      symbols, the headline stream coded at n = 16 (two-level table), the split
+      metadata unpacked on the device against the host planner, the small Laplace
+      stream, and the host-to-device upload;
   c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8 and uint16,
       n 10..12, about 8 KiB per split) decoded by one hipGraph replay of the
       persistent batched kernel (autotuned launch shape) versus one single-stream
@@ -486,6 +488,36 @@ def run_conventional(args, base, torch, np, rc):
     return rows
 
 
+def run_wide(args, base, torch, np, rc):
+    """n = 16 (Table 3's largest quantisation level; the paper's n = 16 columns):
+    the headline stream coded at n = 16 with the same split count, decoded through
+    the two-level LDS table (two table reads per symbol). Container bytes against
+    the n = 12 coding, decoded GB/s, exactness and the roofline position."""
+    s, spec, b12 = base["symbols"], base["spec"], base["blob"]
+    blob = rc.encode(s, lanes=spec.lanes, quant_bits=16, splits=spec.splits)
+    info = blob.info
+    plan = rc.Plan(blob)
+    ws = plan.allocate_workspace()
+    plan.upload(ws)
+    out = plan.allocate_output()
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t = time_decode(plan, ws, out, err, args.steps, args.warmup, torch)
+    exact = check_exact(plan, out, s, err, np)
+    sh = plan.shape()
+    alg = (spec.n_symbols * spec.symbol_bytes + 2 * info.n_words + sh.runs * (20 + 4 * info.lanes)
+           + (4 << 12) + 8 * 256)
+    gbs = spec.n_symbols * spec.symbol_bytes / (t["ms_per_step"] * 1e-3) / 1e9
+    log(f"n=16 W={spec.lanes}: {t['ms_per_step']:.4f} ms/step, {gbs:.1f} GB/s, {info.total_bytes} B "
+        f"(n=12: {b12.info.total_bytes} B), exact={exact}")
+    row = {"decoded_gbs": round(gbs, 2), "ms_per_step": round(t["ms_per_step"], 5), "exact": exact,
+           "container_bytes": info.total_bytes, "n12_container_bytes": b12.info.total_bytes,
+           "launch": {"blocks": sh.blocks, "waves_per_block": sh.waves_per_block, "units_per_run": sh.units_per_run,
+                      "runs": sh.runs, "units_per_wave": sh.units_per_wave},
+           "roofline": roofline(f"decode_units_c1_w{spec.lanes}_n16", "decode_units", alg, t["kernel_ms_mean"])}
+    del ws, out, err, plan, blob
+    return row
+
+
 def run_adaptive(args, torch, np, rc, synth):
     """Adaptive coding (Sec. 3.1; the paper's image latents, Sec. 5.1, stand-in): 128 Mi
     uint8 symbols over 64 values, each drawn from one of 16 Laplace tables chosen by a
@@ -904,6 +936,7 @@ def main():
     if "cache_cold" in base:
         extras["cache_cold"] = base["cache_cold"]
     if not args.no_extras:
+        extras["n16"] = run_wide(args, base, torch, np, rc)
         # The same stream interleaved the other way (the workload names both), and
         # the split-count sweep on the W = 32 encoding.
         other_lanes = 32 if args.lanes == 64 else 64

@@ -93,7 +93,8 @@ enum {
 
 typedef struct {
     uint32_t lanes;         /* W: 32 or 64 for GPU decoding (1..64 accepted by the encoder) */
-    uint32_t quant_bits;    /* n: 1..16 accepted by the encoder; GPU decoding needs 8 <= n <= 12 */
+    uint32_t quant_bits;    /* n: 1..16 accepted by the encoder; GPU decoding needs 8 <= n <= 16 (n > 12:
+                               single-stream decode, at most 4096 symbols with f > 0, not adaptive) */
     uint32_t symbol_bytes;  /* 1 (uint8) or 2 (uint16) */
     uint32_t alphabet;      /* A: symbols lie in [0, A); A <= 256 for uint8, <= 65536 for uint16 */
 } recoil_config;
@@ -234,7 +235,10 @@ void recoil_blob_free(recoil_blob *blob);
  * device-friendly layout and reports the device workspace it needs. The plan
  * keeps its own reference to the blob's data; the blob may be freed first.
  * device_bytes: receives the workspace size (bytes, 256-byte aligned sections).
- * Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n outside 8..12, N or B >= 2^32).
+ * For 13 <= n <= 16 (Table 3 allows n <= 16 with b = 16) the decode table has two
+ * levels so that it fits LDS: 16-slot buckets, then one entry per symbol with f > 0.
+ * Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n outside 8..16, N or B >= 2^32;
+ * n > 12 with more than 4096 symbols of f > 0 or with adaptive tables).
  */
 recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, size_t *device_bytes);
 /* Copy bitstream, decode table and unpacked metadata into the caller-owned
@@ -282,6 +286,16 @@ typedef struct {
     uint32_t unit_count, lanes_per_unit, packed;
 } recoil_plan_layout;
 recoil_status recoil_plan_get_layout(const recoil_plan *plan, recoil_plan_layout *out);
+
+/* The decode table as uploaded (Eq. 2 per slot): for n <= 12, 2^n entries of 4
+ * bytes (uint8: symbol | f << 8 | (slot - F) << 20) or 8 bytes (uint16:
+ * f | (slot - F) << 16, symbol), tables x 2^n of them for adaptive streams; for
+ * 13 <= n <= 16, 2^(n-4) bucket words (bits 16..31: rank of the symbol holding the
+ * bucket's first slot; bit i-1: a symbol's range starts at the bucket's slot i,
+ * i = 1..15) and then per symbol with f > 0, in symbol order, the pair (f,
+ * symbol | F << 16); zero-padded to 16 bytes. dst = NULL: only *bytes is set.
+ * Errors: INVALID_ARG, BUFFER_TOO_SMALL. */
+recoil_status recoil_plan_decode_table(const recoil_plan *plan, void *dst, size_t cap, size_t *bytes);
 /* Launch shape used by recoil_decode for this plan (default: waves 0, i.e. 16
  * per workgroup or 1 for decodes with few runs; K = 8 groups per super-step for
  * uint8 tables, 4 for uint16; units_per_run 0). pairs_per_wave is ignored.

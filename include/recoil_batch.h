@@ -27,7 +27,8 @@ recoil_tuning recoil_default_tuning(void);
  * workspace size (words, tables, unit records, stream descriptors, work items,
  * queue counter) and the output size: stream i's symbols land at the offset given
  * by recoil_batch_output_offset (256-byte aligned). tuning: NULL for the default.
- * Errors: INVALID_ARG, UNSUPPORTED (see recoil_plan_create).
+ * Errors: INVALID_ARG, UNSUPPORTED (see recoil_plan_create; also n > 12 and adaptive
+ * streams, which are decoded alone).
  */
 recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t count, const recoil_tuning *tuning,
                                   recoil_batch **out, size_t *workspace_bytes, size_t *output_bytes);

@@ -266,6 +266,14 @@ class Plan:
         check(_lib.recoil_plan_get_layout(self._h, C.byref(lay)), "recoil_plan_get_layout")
         return lay
 
+    def decode_table(self) -> bytes:
+        """The decode table as uploaded (layout in include/recoil.h)."""
+        n = C.c_size_t()
+        check(_lib.recoil_plan_decode_table(self._h, None, 0, C.byref(n)), "recoil_plan_decode_table")
+        buf = np.zeros(max(n.value, 1), dtype=np.uint8)
+        check(_lib.recoil_plan_decode_table(self._h, _ptr(buf), n.value, C.byref(n)), "recoil_plan_decode_table")
+        return buf[: n.value].tobytes()
+
     def device_records(self, workspace):
         """(units x 4 records, units x W lane words) read back from an uploaded workspace."""
         lay = self.layout()

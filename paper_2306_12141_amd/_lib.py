@@ -74,6 +74,7 @@ class PlanLayout(C.Structure):
 
 
 recoil_plan_get_layout = _sig("recoil_plan_get_layout", [P, C.POINTER(PlanLayout)])
+recoil_plan_decode_table = _sig("recoil_plan_decode_table", [P, P, sz, C.POINTER(sz)])
 
 
 class RecoilError(RuntimeError):

@@ -15,6 +15,8 @@
 //               LDS round trips and no global-memory latency;
 //   decode step slot = x mod 2^n indexes the LDS table; x <- f (x >> n) + slot - F (Eq. 2);
 //               the symbol is stored directly (64 consecutive bytes per wave).
+//               For 13 <= n <= 16 the table has two levels (16-slot buckets,
+//               then one entry per symbol), two LDS reads per symbol.
 // Bitstream ring. Words are fetched in chunks of C = K*W words, the most a unit
 // can consume in K groups (at most one word per symbol, since b >= n). A chunk
 // is requested into registers at the start of a K-group super-step whenever
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
     const uint32_t base = lds_addr(smem);
     {
         const uint4 *src = static_cast<const uint4 *>(p.lut);
-        const uint32_t chunks = (((uint32_t)sizeof(typename Table<Sym>::Entry) << p.quant_bits) * p.tables) / 16;
+        const uint32_t chunks = p.lut_bytes / 16;
         for (uint32_t i = threadIdx.x; i < chunks; i += 64 * WAVES) reinterpret_cast<uint4 *>(lut)[i] = src[i];
     }
     __syncthreads();
@@ -80,16 +82,16 @@ __global__ __launch_bounds__(256) void fill_symbol(Sym *out, uint64_t n, Sym v) 
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) out[i] = v;
 }
 
-template <int W, typename Sym, int K, int WAVES>
-size_t lds_bytes(uint32_t quant_bits, uint32_t tables) {
-    return Lds<0, K, WAVES>::TABLE + ((size_t)sizeof(typename Table<Sym>::Entry) << quant_bits) * tables;
+template <int K, int WAVES>
+size_t lds_bytes(uint32_t lut_bytes) {
+    return Lds<0, K, WAVES>::TABLE + (size_t)lut_bytes;
 }
 
 template <int W, typename Sym, int K, int WAVES, int SS, int VAR>
-int units_occupancy(uint32_t quant_bits, uint32_t tables) {
+int units_occupancy(uint32_t lut_bytes) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_units<W, Sym, K, WAVES, SS, VAR>, 64 * WAVES,
-                                                     lds_bytes<W, Sym, K, WAVES>(quant_bits, tables)) != hipSuccess)
+                                                     lds_bytes<K, WAVES>(lut_bytes)) != hipSuccess)
         return 0;
     return per_cu;
 }
@@ -97,7 +99,7 @@ int units_occupancy(uint32_t quant_bits, uint32_t tables) {
 // Resident workgroups of the kernel with SS units per wave (0: does not fit).
 template <int W, typename Sym, int K, int WAVES, int SS, int VAR>
 uint32_t resident_blocks(const DecodeParams &p, const DecodeTuning &t) {
-    int per_cu = units_occupancy<W, Sym, K, WAVES, SS, VAR>(p.quant_bits, p.tables);
+    int per_cu = units_occupancy<W, Sym, K, WAVES, SS, VAR>(p.lut_bytes);
     if (per_cu < 1) return 0;
     if (t.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)t.blocks_per_cu);
     return (uint32_t)(device_cus() * per_cu);
@@ -118,7 +120,7 @@ hipError_t launch_ss(const DecodeParams &p, const DecodeTuning &t, uint32_t resi
         *shape = DecodeShape{blocks, (uint32_t)WAVES, q.run, q.runs, (uint32_t)SS};
         return hipSuccess;
     }
-    const size_t lds = lds_bytes<W, Sym, K, WAVES>(p.quant_bits, p.tables);
+    const size_t lds = lds_bytes<K, WAVES>(p.lut_bytes);
     hipLaunchKernelGGL((decode_units<W, Sym, K, WAVES, SS, VAR>), dim3(blocks), dim3(64 * WAVES), lds, stream, q);
     return hipGetLastError();
 }
@@ -203,6 +205,16 @@ hipError_t launch_decode(const DecodeParams &p, uint32_t lanes, uint32_t symbol_
             hipLaunchKernelGGL(fill_symbol<uint16_t>, dim3(blocks), dim3(256), 0, stream,
                                static_cast<uint16_t *>(p.out), p.n_symbols, (uint16_t)p.fill_symbol);
         return hipGetLastError();
+    }
+    if (p.lut_bytes % 16 || p.lut_bytes > kMaxTableBytes) return hipErrorInvalidValue;
+    if (p.quant_bits > 12) {
+        // Wide tables (two-level, 13 <= n <= 16): plain decoding only.
+        if (p.counts || p.tidx) return hipErrorInvalidValue;
+        if (lanes == 32 && symbol_bytes == 1) return launch_shape<32, uint8_t, kWide>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 1) return launch_shape<64, uint8_t, kWide>(p, t, stream, shape);
+        if (lanes == 32 && symbol_bytes == 2) return launch_shape<32, uint16_t, kWide>(p, t, stream, shape);
+        if (lanes == 64 && symbol_bytes == 2) return launch_shape<64, uint16_t, kWide>(p, t, stream, shape);
+        return hipErrorInvalidValue;
     }
     if (p.tidx) {
         // Adaptive coding: per-symbol tables, uint8 symbols only.

@@ -20,13 +20,21 @@ struct UnitMeta {
 // (bits 16..31) = top - group of the lane's recorded symbol. For the last unit
 // the word is the full 32-bit final state and every lane is active at once.
 //
-// Decode table entries, indexed by slot = x mod 2^n:
-//   8-bit symbols:  bits 0..7 symbol, 8..19 f(s), 20..31 slot - F(s)     (n <= 12, f < 4096)
+// Decode table entries, indexed by slot = x mod 2^n (n <= 12):
+//   8-bit symbols:  bits 0..7 symbol, 8..19 f(s), 20..31 slot - F(s)     (f < 4096)
 //   16-bit symbols: .x = f(s) | (slot - F(s)) << 16, .y = symbol
+// Wide tables (13 <= n <= 16, either symbol size), in two levels so that they fit
+// LDS: 2^(n-4) bucket words, then one u32x2 per symbol with f > 0 in symbol
+// order (its rank r). Bucket word b covers slots 16b .. 16b+15: bits 16..31 the
+// rank of the symbol holding slot 16b, bit i-1 (i = 1..15) set when a symbol's
+// range starts at slot 16b + i. Rank entry: .x = f(s), .y = s | F(s) << 16.
 //
 // The words array handed to the kernels is readable (padding) up to the next
 // multiple of kChunkPadWords past B, because bitstream chunks are fetched whole.
 constexpr uint32_t kChunkPadWords = 1024;
+
+// Largest decode table staged in LDS (adaptive tables, wide tables).
+constexpr uint32_t kMaxTableBytes = 65536;
 
 struct DecodeParams {
     const uint16_t *words;      // B words (+ padding, see above)
@@ -38,6 +46,7 @@ struct DecodeParams {
     uint32_t *counts;           // checking launches only: N per-symbol store counts (else NULL)
     const uint8_t *tidx;        // adaptive coding: N per-symbol table indices (else NULL)
     uint32_t tables;            // decode tables in lut (1 unless adaptive)
+    uint32_t lut_bytes;         // bytes of lut staged in LDS (a multiple of 16)
     uint64_t n_symbols;
     uint32_t units;
     uint32_t run;               // consecutive units decoded as one (Sec. 3.3): 1 uses every split point

@@ -91,6 +91,22 @@ struct Table<uint16_t> {
     }
 };
 
+// Wide tables (13 <= n <= 16): the two-level layout of decode.hpp. The symbol's
+// rank is the bucket's first rank plus the range starts between the bucket's first
+// slot and this one (a popcount of the low p start bits, p = slot mod 16).
+template <typename Sym>
+struct WideTable {
+    using Entry = u32x2;
+    __device__ static inline uint32_t step(uint32_t lut, uint32_t &x, uint32_t n, uint32_t mask) {
+        const uint32_t slot = x & mask;
+        const uint32_t c = lds_ld<uint32_t>(lut + ((slot >> 4) << 2));
+        const uint32_t r = (c >> 16) + __builtin_popcount(__builtin_amdgcn_ubfe(c, 0, slot & 15u));
+        const Entry e = lds_ld<Entry>(lut + ((mask + 1u) >> 2) + (r << 3));
+        x = __umul24(e.x, x >> n) + slot - (e.y >> 16);
+        return e.y;
+    }
+};
+
 template <int W, int K, int SS = 64 / W>
 struct Geo {
     static constexpr uint32_t S = SS;                 // units per wave (W = 32: one per half-wave, or one)
@@ -154,13 +170,13 @@ __device__ inline T uni_load(const T *src) {
 
 // Kernel variants: kCount also adds 1 to counts[i] for every store of symbol i (a
 // checking launch); kAdaptive codes symbol i with decode table tidx[i] (adaptive
-// coding, uint8 symbols).
-constexpr int kPlain = 0, kCount = 1, kAdaptive = 2;
+// coding, uint8 symbols); kWide reads the two-level table of 13 <= n <= 16.
+constexpr int kPlain = 0, kCount = 1, kAdaptive = 2, kWide = 3;
 
 template <int W, typename Sym, int K, int SS = 64 / W, int VAR = kPlain>
 struct PairDecoder {
     using G = Geo<W, K, SS>;
-    using T = Table<Sym>;
+    using T = typename std::conditional<VAR == kWide, WideTable<Sym>, Table<Sym>>::type;
     using Chunk = typename G::Chunk;
     static constexpr uint32_t S = G::S, C = G::C, R = G::R;
     static constexpr bool COUNT = VAR == kCount, ADAPT = VAR == kAdaptive;

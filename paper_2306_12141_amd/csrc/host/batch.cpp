@@ -171,6 +171,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     for (uint32_t i = 0; i < count; ++i) {
         if (!blobs[i]) { delete h; return fail(RECOIL_ERR_INVALID_ARG, "batch_create: NULL blob"); }
         if (blobs[i]->data->adaptive) { delete h; return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: adaptive streams are decoded alone"); }
+        if (blobs[i]->data->quant_bits > 12) { delete h; return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: n > 12 streams are decoded alone"); }
         recoil_status st = build_plan(blobs[i]->data, b.plans[i]);
         if (st) { delete h; return st; }
         b.lut_bytes = std::max<uint32_t>(b.lut_bytes, (uint32_t)b.plans[i].lut.size());
@@ -352,6 +353,7 @@ recoil_status recoil_decode_batch_per_stream(const recoil_batch *batch, const vo
         p.single_symbol = d.single_symbol;
         p.partitioned = d.partitioned;
         p.tables = 1;
+        p.lut_bytes = (uint32_t)pl.lut.size();
         hipError_t e = launch_decode(p, pl.blob->lanes, pl.blob->symbol_bytes, pl.tuning, stream);
         if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("decode_batch_per_stream: ") + hipGetErrorString(e));
     }

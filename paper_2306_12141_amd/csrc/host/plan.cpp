@@ -28,13 +28,22 @@ recoil_status check_gpu_limits(const BlobData &b) {
     const uint32_t W = b.lanes, n = b.quant_bits;
     if (W != 32 && W != 64) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs W = 32 or 64");
     // Eq. 2 is evaluated with a 24-bit multiply, f (x >> n): x >> n fits 24 bits only for n >= 8.
-    if (n < 8 || n > 12) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 12");
+    if (n < 8 || n > 16) return fail(RECOIL_ERR_UNSUPPORTED, "plan: GPU decoding needs 8 <= n <= 16");
     if (b.n_symbols >= (1ull << 32) || b.n_words() + kChunkPadWords >= (1ull << 31))
         return fail(RECOIL_ERR_UNSUPPORTED, "plan: N must be below 2^32 and B below 2^31 - 1024 words");
     if (b.symbol_bytes == 2 && b.alphabet > 65536) return fail(RECOIL_ERR_UNSUPPORTED, "plan: alphabet too large");
-    if (b.adaptive && (b.symbol_bytes != 1 || ((uint64_t)b.tables << (n + 2)) > kMaxAdaptiveTableBytes))
-        return fail(RECOIL_ERR_UNSUPPORTED, "plan: adaptive decoding needs uint8 symbols and tables x 2^n x 4 <= 64 KiB");
+    if (b.adaptive && (n > 12 || b.symbol_bytes != 1 || ((uint64_t)b.tables << (n + 2)) > kMaxAdaptiveTableBytes))
+        return fail(RECOIL_ERR_UNSUPPORTED,
+                    "plan: adaptive decoding needs uint8 symbols, n <= 12 and tables x 2^n x 4 <= 64 KiB");
+    if (n > 12 && wide_ranks(b) > kMaxWideRanks)
+        return fail(RECOIL_ERR_UNSUPPORTED, "plan: n > 12 decoding needs at most 4096 symbols with f > 0");
     return RECOIL_OK;
+}
+
+uint32_t wide_ranks(const BlobData &b) {
+    uint32_t r = 0;
+    for (uint32_t s = 0; s < b.alphabet; ++s) r += b.freq[s] != 0;
+    return r;
 }
 
 recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &pl) {
@@ -47,7 +56,7 @@ recoil_status build_units(const std::shared_ptr<const BlobData> &bp, PlanData &p
     // launches with few runs), 8-group super-steps when the table is small enough
     // for two 16-wave workgroups per CU (uint8 symbols), 4-group otherwise.
     pl.tuning.waves = 0;
-    pl.tuning.chunk_groups = b.symbol_bytes == 1 && !b.adaptive ? 8 : 4;
+    pl.tuning.chunk_groups = default_chunk_groups(b);
     pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
     pl.meta.resize(M);
@@ -114,7 +123,7 @@ recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, ui
     pl.blob = bp;
     pl.units = Mc;
     pl.tuning.waves = 0;
-    pl.tuning.chunk_groups = b.symbol_bytes == 1 ? 8 : 4;
+    pl.tuning.chunk_groups = default_chunk_groups(b);
     pl.tuning.blocks_per_cu = 0;
     const uint64_t G = b.groups();
     pl.meta.resize(Mc);
@@ -160,6 +169,31 @@ recoil_status build_units_combined(const std::shared_ptr<const BlobData> &bp, ui
     return RECOIL_OK;
 }
 
+// Wide decode table (13 <= n <= 16): 16-slot buckets, then one entry per symbol
+// with f > 0 (layout in decode.hpp).
+void build_wide_table(const BlobData &b, PlanData &pl) {
+    const uint32_t n = b.quant_bits, buckets = 1u << (n - 4);
+    std::vector<uint32_t> bucket(buckets, 0);
+    std::vector<uint32_t> ranks;
+    uint32_t F = 0, r = 0;
+    for (uint32_t s = 0; s < b.alphabet; ++s) {
+        const uint32_t f = b.freq[s];
+        if (!f) continue;
+        // Symbol s holds slots F .. F+f-1: it is the first of every bucket it covers
+        // from the start, and marks its start inside the bucket holding slot F.
+        if (F % 16) bucket[F / 16] |= 1u << (F % 16 - 1);
+        for (uint32_t q = (F + 15) / 16; q * 16 < F + f; ++q) bucket[q] |= r << 16;
+        ranks.push_back(f);
+        ranks.push_back(s | (F << 16));
+        F += f;
+        ++r;
+    }
+    const size_t bytes = 4 * (size_t)buckets + 4 * ranks.size();
+    pl.lut.assign((bytes + 15) / 16 * 16, 0);
+    std::memcpy(pl.lut.data(), bucket.data(), 4 * (size_t)buckets);
+    std::memcpy(pl.lut.data() + 4 * (size_t)buckets, ranks.data(), 4 * ranks.size());
+}
+
 // Decode table: slot -> (symbol, f, slot - F) for the 2^n slots (Eq. 2).
 void build_table(const BlobData &b, PlanData &pl) {
     const uint32_t slots = 1u << b.quant_bits;
@@ -168,6 +202,10 @@ void build_table(const BlobData &b, PlanData &pl) {
         if (b.freq[s]) { ++present; only = s; }
     pl.single_symbol = present == 1 && !b.adaptive;
     pl.fill_symbol = only;
+    if (b.quant_bits > 12) {
+        build_wide_table(b, pl);
+        return;
+    }
     const size_t esz = b.symbol_bytes == 1 ? 4 : 8;
     // Adaptive coding: the tables' decode tables end to end, table t at slot t 2^n.
     pl.lut.assign((size_t)slots * esz * b.tables, 0);
@@ -216,7 +254,7 @@ recoil_status build_plan_packed(const std::shared_ptr<const BlobData> &bp, uint3
     pl.step = (uint32_t)ceil_div(M, target == 0 ? M : std::min(target, M));
     pl.units = (M - 1) / pl.step + 1;
     pl.tuning.waves = 0;
-    pl.tuning.chunk_groups = b.symbol_bytes == 1 && !b.adaptive ? 8 : 4;
+    pl.tuning.chunk_groups = default_chunk_groups(b);
     pl.tuning.blocks_per_cu = 0;
     pl.packed_bits.assign(b.meta_bits.size() + 8, 0);
     std::copy(b.meta_bits.begin(), b.meta_bits.end(), pl.packed_bits.begin());
@@ -299,6 +337,17 @@ size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan) {
     const recoil::PlanData &pl = plan->d;
     if (pl.packed) return pl.blob->meta_bits.size() + pl.block_bit.size() * 4 + (size_t)pl.blob->lanes * 4;
     return pl.meta.size() * sizeof(recoil::UnitMeta) + pl.lanes.size() * 4;
+}
+
+recoil_status recoil_plan_decode_table(const recoil_plan *plan, void *dst, size_t cap, size_t *bytes) {
+    using namespace recoil;
+    if (!plan) return fail(RECOIL_ERR_INVALID_ARG, "plan_decode_table: NULL plan");
+    const std::vector<uint8_t> &t = plan->d.lut;
+    if (bytes) *bytes = t.size();
+    if (!dst) return RECOIL_OK;
+    if (cap < t.size()) return fail(RECOIL_ERR_BUFFER_TOO_SMALL, "plan_decode_table: buffer too small");
+    std::memcpy(dst, t.data(), t.size());
+    return RECOIL_OK;
 }
 
 recoil_status recoil_plan_get_layout(const recoil_plan *plan, recoil_plan_layout *out) {
@@ -384,6 +433,7 @@ recoil::DecodeParams decode_params(const recoil::PlanData &pl, const void *d_ws,
     p.single_symbol = pl.single_symbol ? 1u : 0u;
     p.partitioned = b.partitioned() ? 1u : 0u;
     p.tables = b.tables;
+    p.lut_bytes = (uint32_t)pl.lut.size();
     p.tidx = nullptr;
     return p;
 }

@@ -33,6 +33,15 @@ struct PlanData {
 constexpr size_t kWsAlign = 256;
 // Adaptive coding: the decode tables of all tables must fit LDS beside the rings.
 constexpr uint64_t kMaxAdaptiveTableBytes = 65536;
+// Wide tables (n > 12): symbols with f > 0, at 8 bytes each beside 16 KiB of buckets.
+constexpr uint32_t kMaxWideRanks = 4096;
+// Symbols with f > 0 (the entries of a wide table).
+uint32_t wide_ranks(const BlobData &b);
+// Groups per super-step of the default launch shape: 8 for uint8 tables of n <= 12
+// (two 16-wave workgroups per CU still fit LDS), else 4.
+inline uint32_t default_chunk_groups(const BlobData &b) {
+    return b.symbol_bytes == 1 && !b.adaptive && b.quant_bits <= 12 ? 8u : 4u;
+}
 inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
 // Unpack split metadata and build the decode table; fills the single-stream layout.

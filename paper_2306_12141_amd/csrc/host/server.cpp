@@ -592,6 +592,7 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
     if (bp->partitioned())   // requests ask for a unit count, which a partitioned stream cannot give
         return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: partitioned streams cannot be combined per request");
     if (bp->adaptive) return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: adaptive streams are decoded alone");
+    if (bp->quant_bits > 12) return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: n > 12 streams are decoded alone");
     PlanData probe;
     recoil_status st = build_units(bp, probe);   // checks the GPU decoder's limits
     if (st) return st;

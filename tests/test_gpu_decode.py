@@ -470,3 +470,45 @@ def test_adaptive_streams(rc, orc, W, n, T, A, nbits, M, run):
         assert not np.array_equal(plan.symbols_of(out), s)
     with pytest.raises(rc.RecoilError):
         plan.decode(ws, out, err)                   # the index is required
+
+
+WIDE_CASES = [
+    # (lanes, n, symbol dtype, alphabet, N, splits, zipf exponent or None): 13 <= n <= 16
+    (32, 16, np.uint8, 256, (1 << 20) + 5, 64, 1.1),
+    (64, 16, np.uint8, 256, 300_001, 37, 0.9),
+    (32, 13, np.uint8, 256, 200_000, 20, 1.2),
+    (64, 14, np.uint8, 200, 150_000, 9, None),
+    (32, 16, np.uint8, 256, 100_000, 12, None),      # uniform: every f = 256, no start inside a bucket
+    (32, 16, np.uint8, 2, 40_000, 30, 3.0),
+    (32, 15, np.uint16, 4096, 200_003, 30, 1.0),
+    (64, 16, np.uint16, 4096, 120_003, 20, 1.3),
+    (32, 13, np.uint16, 4096, 100_000, 16, None),    # f = 2: eight starts in every bucket
+    (32, 16, np.uint8, 256, 31, 4, None),            # N < W
+    (64, 16, np.uint8, 256, 65, 4, None),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(WIDE_CASES)),
+                         ids=[f"W{c[0]}_n{c[1]}_{np.dtype(c[2]).name}_N{c[4]}_M{c[5]}" for c in WIDE_CASES])
+def test_wide_tables(rc, ci):
+    """13 <= n <= 16: the two-level LDS table (16-slot buckets, per-symbol entries)
+    with the default shape, 8-group super-steps, one unit per run, and combined."""
+    W, n, dt, A, N, M, z = WIDE_CASES[ci]
+    _say("case wide", WIDE_CASES[ci])
+    s = _syms(6000 + ci, N, A, dt, z)
+    blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
+    assert np.array_equal(gpu_decode(rc, blob), s)
+    assert np.array_equal(gpu_decode(rc, blob, waves=16, chunk_groups=8), s)
+    assert np.array_equal(gpu_decode(rc, blob, waves=8, chunk_groups=4, units_per_run=1), s)
+    if M > 2:
+        assert np.array_equal(gpu_decode(rc, blob.combine(M // 3)), s)
+
+
+@pytest.mark.parametrize("W", [32, 64])
+def test_wide_full_size(rc, W):
+    """The 256 MiB Zipf(1.1) stream of the headline workload, coded at n = 16."""
+    spec = synth.c1_spec(W)
+    s = spec.generate()
+    _say("case wide full", W)
+    blob = rc.encode(s, lanes=W, quant_bits=16, splits=spec.splits)
+    assert np.array_equal(gpu_decode(rc, blob), s)

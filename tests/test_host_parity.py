@@ -183,8 +183,7 @@ def test_plan_rejects_unsupported(rc):
     s = _syms(3, 10_000, 256)
     with pytest.raises(rc.RecoilError):
         rc.Plan(rc.encode(s, lanes=16, quant_bits=11, splits=4))
-    with pytest.raises(rc.RecoilError):
-        rc.Plan(rc.encode(s, lanes=32, quant_bits=13, splits=4))
+    rc.Plan(rc.encode(s, lanes=32, quant_bits=13, splits=4))   # n <= 16 (Table 3), two-level table
     # Eq. 2 on the GPU multiplies f by x >> n in 24 bits, which holds only for n >= 8.
     with pytest.raises(rc.RecoilError) as e:
         rc.Plan(rc.encode(s % 64, lanes=32, quant_bits=7, splits=4, alphabet=64))
@@ -266,3 +265,31 @@ def test_adaptive_plan_limits(rc, orc):
     tabs, tidx, s = _adaptive_case(orc, 9, 10_000, 32, 64, 10)       # 32 x 1024 x 4 B = 128 KiB
     with pytest.raises(rc.RecoilError):
         rc.Plan(rc.encode_adaptive(s, tabs, tidx, lanes=32, quant_bits=10, splits=4, alphabet=64))
+
+
+@pytest.mark.parametrize("W,n,dt,A,N,M,z", [(64, 16, np.uint8, 256, 100_000, 30, 1.1),
+                                            (32, 13, np.uint8, 256, 50_000, 8, None),
+                                            (32, 15, np.uint16, 4096, 60_000, 9, 1.0)])
+def test_wide_byte_identical_and_planned(rc, orc, W, n, dt, A, N, M, z):
+    """13 <= n <= 16: containers equal the oracle's and the GPU planner accepts them."""
+    s = _syms(7000 + n, N, A, dt, z)
+    blob = rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A)
+    p = orc.params(lanes=W, quant_bits=n, symbol_bytes=np.dtype(dt).itemsize, alphabet=A)
+    assert blob.to_bytes() == orc.encode(s, p, M).container()
+    plan = rc.Plan(blob)
+    assert plan.units().shape == (blob.splits, 4)
+    assert rc.Plan(blob, packed_target=0).layout().unit_count == blob.splits
+
+
+def test_wide_limits(rc):
+    """n > 12 decodes on the GPU only with at most 4096 symbols of f > 0, without
+    adaptive tables, and in the single-stream path only."""
+    s = (synth.splitmix64(7100, 0, 200_000) % np.uint64(60000)).astype(np.uint16)
+    blob = rc.encode(s, lanes=32, quant_bits=16, splits=4, alphabet=60000)
+    with pytest.raises(rc.RecoilError, match="unsupported"):
+        rc.Plan(blob)
+    ok = rc.encode((s % 4096).astype(np.uint16), lanes=32, quant_bits=16, splits=4, alphabet=4096)
+    rc.Plan(ok)
+    from paper_2306_12141_amd import batch
+    with pytest.raises(rc.RecoilError, match="unsupported"):
+        batch.Batch([ok])
