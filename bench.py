@@ -632,10 +632,16 @@ def run_c3(args, torch, np, rc, synth):
     torch.cuda.synchronize()
     n_items = batch.items
     log(f"C3: {n_items} work items, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
-    best, best_ms = batch.autotune(ws, out, err, reps=3)
+    if args.c3_tuning:
+        from paper_2306_12141_amd._lib import Tuning
+        v = [int(x) for x in args.c3_tuning.split(",")]
+        best, best_ms = Tuning(v[0], v[1], v[2], 0, v[3]), -1.0
+        batch.set_tuning(best, ws)
+    else:
+        best, best_ms = batch.autotune(ws, out, err, reps=3)
     shape = {"waves": best.waves, "chunk_groups": best.chunk_groups, "pairs_per_wave": best.pairs_per_wave,
              "units_per_run": best.units_per_run}
-    log(f"C3: autotuned {shape} ({best_ms:.3f} ms)")
+    log(f"C3: {'set' if args.c3_tuning else 'autotuned'} {shape} ({best_ms:.3f} ms)")
     graph = batch.graph(ws, out, err)
     stream = torch.cuda.current_stream()
 
@@ -655,8 +661,12 @@ def run_c3(args, torch, np, rc, synth):
     exact_batched, bad_b = all_exact()
     out.fill_(0xA5)
     ps_steps = max(3, args.steps // 4)
-    p_mean, p_med = _time_launches(lambda: batch.decode_per_stream(ws, out, err), ps_steps, 1, torch)
-    exact_ps, bad_p = all_exact()
+    if args.c3_batched_only:
+        p_mean = p_med = float("nan")
+        exact_ps, bad_p = True, 0
+    else:
+        p_mean, p_med = _time_launches(lambda: batch.decode_per_stream(ws, out, err), ps_steps, 1, torch)
+        exact_ps, bad_p = all_exact()
     value = out_bytes / (g_mean * 1e-3) / 1e9
     per_stream = out_bytes / (p_mean * 1e-3) / 1e9
     log(f"C3: batched {value:.1f} GB/s ({g_mean:.3f} ms), per-stream {per_stream:.1f} GB/s ({p_mean:.3f} ms), "
@@ -679,10 +689,11 @@ def run_c3(args, torch, np, rc, synth):
                    "streams": len(streams), "decoded_bytes": out_bytes, "words_bytes": words_bytes,
                    "metadata_bytes": meta_bytes, "work_items": n_items, "tuning": shape,
                    "streams_checked": len(streams)},
-        "per_stream": {"value": round(per_stream, 3), "unit": "GB/s", "ms": round(p_mean, 5),
-                       "ms_median": round(p_med, 5), "launches": len(streams), "exact": exact_ps,
-                       "how": "one single-stream recoil_decode launch per stream, in order, on one HIP stream"},
-        "speedup_vs_per_stream": round(p_mean / g_mean, 3),
+        "per_stream": None if args.c3_batched_only else {
+            "value": round(per_stream, 3), "unit": "GB/s", "ms": round(p_mean, 5),
+            "ms_median": round(p_med, 5), "launches": len(streams), "exact": exact_ps,
+            "how": "one single-stream recoil_decode launch per stream, in order, on one HIP stream"},
+        "speedup_vs_per_stream": None if args.c3_batched_only else round(p_mean / g_mean, 3),
         "batched_ms_median": round(g_med, 5), "autotune_best_ms": round(best_ms, 4),
         "roofline": roofline("decode_batch_c3", "decode_batch", alg, g_mean,
                              timing="mean over the timed graph replays, HIP events around each replay"),
@@ -876,10 +887,14 @@ def main():
                     help="interleaved lanes of the headline encoding (the other is reported in extras)")
     ap.add_argument("--shape", default="", metavar="WAVES,K,BLOCKS_PER_CU[,UNITS_PER_RUN]",
                     help="launch shape of the decode kernel (default 16,8,0,0: units per run chosen at launch)")
-    ap.add_argument("--workload", default="all", choices=("all", "c1", "c3", "c4"),
+    ap.add_argument("--workload", default="all", choices=("all", "c1", "c3", "c4", "n16"),
                     help="all (default): the headline line with c3 and c4 in it; c1: without them; "
-                         "c3 / c4: that workload's own line")
+                         "c3 / c4 / n16: that workload's own line (n16: the headline stream coded at n = 16)")
     ap.add_argument("--c3-streams", type=int, default=4096, help="streams in the batched workload")
+    ap.add_argument("--c3-tuning", default="", metavar="WAVES,K,PAIRS,UNITS_PER_RUN",
+                    help="batched launch shape instead of the autotuner's choice")
+    ap.add_argument("--c3-batched-only", action="store_true",
+                    help="skip the per-stream launches (for counter runs of the batched kernel)")
     ap.add_argument("--c4-corpus", type=int, default=128, help="resident streams in the serving corpus")
     ap.add_argument("--c4-rate", type=float, default=2000.0, help="request arrival rate (1/s)")
     ap.add_argument("--c4-seconds", type=float, default=30.0, help="measured window after warm-up (s)")
@@ -925,6 +940,19 @@ def main():
                 "config": sub["config"], "roofline": sub["roofline"], "cpu_baseline": sub["cpu_baseline"],
                 "extras": {k: v for k, v in sub.items() if k not in ("value", "unit", "config", "roofline",
                                                                    "cpu_baseline")}}
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "n16":
+        base = run_c1(argparse.Namespace(**{**vars(args), "no_extras": True}), torch, np, rc, synth)
+        row = run_wide(args, base, torch, np, rc)
+        line = {"metric": METRIC, "value": row["decoded_gbs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": row["ms_per_step"], "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+                "data": "synthetic (seeded SplitMix64 streams; the paper's corpora are not available)",
+                "config": {"workload": f"single 256 MiB uint8 stream, Zipf(1.1) over a seeded permutation of 256 "
+                                       f"symbols, n=16, W={args.lanes}, {base['blob_info'].splits} splits"},
+                "roofline": row["roofline"], "cpu_baseline": None,
+                "extras": {k: v for k, v in row.items() if k != "roofline"}}
         print(json.dumps(line), flush=True)
         return
     base = run_c1(args, torch, np, rc, synth)
