@@ -29,7 +29,7 @@ The same line also carries (each bit-exact against the input symbols):
 Each carries `roofline` (HBM and ALU ceilings of its dominant kernel) and
 `cpu_baseline` (the CPU oracle on a bounded sample of the same workload).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c1|c3|c4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|c1|c3|c4|n16]
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
 
@@ -121,6 +121,8 @@ def roofline(key: str, kernel: str, alg_bytes: int, kernel_ms: float, **extra) -
            "unit": top["unit"], "frac": top["frac"], "traffic": measured_traffic(key, kernel), "kernel": kernel,
            "alg_bytes_per_launch": alg_bytes, "kernel_ms_mean": round(kernel_ms, 5), "hbm": hbm, "alu": alu}
     out.update(extra)
+    if alu is None and not cnt:
+        out["alu_note"] = f"no committed counter run of this kernel source for {key}"
     return out
 
 
@@ -695,7 +697,9 @@ def run_c3(args, torch, np, rc, synth):
             "how": "one single-stream recoil_decode launch per stream, in order, on one HIP stream"},
         "speedup_vs_per_stream": None if args.c3_batched_only else round(p_mean / g_mean, 3),
         "batched_ms_median": round(g_med, 5), "autotune_best_ms": round(best_ms, 4),
-        "roofline": roofline("decode_batch_c3", "decode_batch", alg, g_mean,
+        "roofline": roofline("decode_batch_c3@" + ",".join(str(shape[k]) for k in ("waves", "chunk_groups",
+                                                                                    "pairs_per_wave", "units_per_run")),
+                             "decode_batch", alg, g_mean,
                              timing="mean over the timed graph replays, HIP events around each replay"),
         "cpu_baseline": cpu,
     }
