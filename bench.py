@@ -14,8 +14,9 @@ The same line also carries (each bit-exact against the input symbols):
       65536 / 16384 / 256 sub-sequences against Recoil at the same parallelism,
       adaptive coding (16 per-symbol tables) against one static table on the same
       symbols, the headline stream coded at n = 16 (two-level table), the split
-      metadata unpacked on the device against the host planner, the small Laplace
-      stream, and the host-to-device upload;
+      metadata unpacked on the device against the host planner, the host encode
+      with the streaming and the threaded split writer, the small Laplace stream,
+      and the host-to-device upload;
   c3: 4096 mixed streams (4 KiB..16 MiB, Laplace/Zipf/uniform, uint8 and uint16,
       n 10..12, about 8 KiB per split) decoded by one hipGraph replay of the
       persistent batched kernel (autotuned launch shape) versus one single-stream
@@ -458,6 +459,32 @@ def run_unpack(args, base, torch, np, rc):
             f"exact={exact}")
         del ws_p, out, err, host, packed, hb
     return rows
+
+
+def run_split_writer(args, base, torch, np, rc):
+    """Host encode time of the stream with the streaming split chooser against the
+    threaded split writer (same split points: containers compared byte for byte)."""
+    s, spec, ref = base["symbols"], base["spec"], base["blob"].to_bytes()
+    row = {"symbols": spec.n_symbols, "lanes": spec.lanes, "splits": spec.splits, "host_cores": host_cores()}
+    try:
+        for name, t in (("streaming", 1), ("threaded", 0)):
+            rc.set_split_writer_threads(t)
+            t0 = time.perf_counter()
+            b = rc.encode(s, lanes=spec.lanes, quant_bits=spec.quant_bits, splits=spec.splits)
+            row[f"{name}_encode_s"] = round(time.perf_counter() - t0, 3)
+            row[f"{name}_identical"] = b.to_bytes() == ref
+            del b
+    finally:
+        rc.set_split_writer_threads(0)
+    rc.set_split_writer_threads(1)
+    t0 = time.perf_counter()
+    rc.encode(s, lanes=spec.lanes, quant_bits=spec.quant_bits, splits=1)
+    row["no_splits_encode_s"] = round(time.perf_counter() - t0, 3)
+    rc.set_split_writer_threads(0)
+    log(f"split writer: streaming {row['streaming_encode_s']} s, threaded {row['threaded_encode_s']} s, "
+        f"encode without splits {row['no_splits_encode_s']} s, identical {row['streaming_identical']}/"
+        f"{row['threaded_identical']}")
+    return row
 
 
 def run_conventional(args, base, torch, np, rc):
@@ -986,6 +1013,7 @@ def main():
         extras["combined_w32"] = run_combined(args, w32, torch, np, rc)
         extras["conventional_w32"] = run_conventional(args, w32, torch, np, rc)
         extras["device_unpack_w32"] = run_unpack(args, w32, torch, np, rc)
+        extras["split_writer_w32"] = run_split_writer(args, w32, torch, np, rc)
         extras["adaptive"] = run_adaptive(args, torch, np, rc, synth)
         del other, w32
         extras["c0"] = run_c0(args, torch, np, rc, synth)

@@ -212,6 +212,18 @@ recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols,
                                         const uint32_t *freq, uint32_t partitions, recoil_blob **out);
 
 /*
+ * Split selection of the encoders (Sec. 4.1, Def. 4.1): threads = 1 uses the
+ * streaming chooser inside the encoder's pass; threads >= 2 has the encoder keep a
+ * log of its renormalisation events (6 bytes per word) and chooses afterwards with
+ * that many threads (a segmented per-lane latest-event scan over word chunks, then
+ * the greedy choice over the words in order); 0 (the default) picks the threaded
+ * form for streams of 2^24 symbols or more. Every setting chooses the same split
+ * points, so the containers are byte-identical. Process-wide; takes effect for
+ * encodes started after the call.
+ */
+void recoil_set_split_writer_threads(uint32_t threads);
+
+/*
  * Decoder-adaptive combining (Sec. 3.3, end of Sec. 4.2): keep every
  * ceil(M_in / target)-th split point, which leaves ceil(M_in / step) decode
  * units (exactly `target` when it divides M_in), and re-express the stored

@@ -84,6 +84,12 @@ class Blob:
         return Blob(h)
 
 
+def set_split_writer_threads(threads: int) -> None:
+    """Split selection: 1 streaming (inside the encoder's pass), >= 2 threaded after
+    it, 0 automatic (threaded from 2^24 symbols). Same split points either way."""
+    _lib.recoil_set_split_writer_threads(int(threads))
+
+
 def encode(symbols: np.ndarray, lanes: int = 32, quant_bits: int = 11, splits: int = 1,
            alphabet: Optional[int] = None, freq: Optional[np.ndarray] = None) -> Blob:
     """Encode uint8/uint16 symbols into one interleaved stream with `splits` decode units."""

@@ -53,6 +53,7 @@ recoil_encode_adaptive = _sig("recoil_encode_adaptive", [P, u64, C.POINTER(Confi
 recoil_decode_adaptive = _sig("recoil_decode_adaptive", [P, P, P, P, P, P])
 recoil_encode_partitioned = _sig("recoil_encode_partitioned", [P, u64, C.POINTER(Config), P, u32, C.POINTER(P)])
 recoil_combine_splits = _sig("recoil_combine_splits", [P, u32, C.POINTER(P)])
+recoil_set_split_writer_threads = _sig("recoil_set_split_writer_threads", [u32], None)
 recoil_blob_serialize = _sig("recoil_blob_serialize", [P, P, sz, C.POINTER(sz)])
 recoil_blob_deserialize = _sig("recoil_blob_deserialize", [P, sz, C.POINTER(P)])
 recoil_blob_info = _sig("recoil_blob_info", [P, C.POINTER(BlobInfo)])

@@ -5,9 +5,11 @@
 // renormalisation), Sec. 2.2 (interleaving), Sec. 4.1 (backward scan), Def. 4.1
 // (split heuristic), Sec. 3.3 (combining), Sec. 4.3 (metadata storage).
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <queue>
+#include <thread>
 #include <utility>
 
 #include "blob.hpp"
@@ -281,6 +283,191 @@ private:
     std::vector<Cand> cand_;
 };
 
+// --------------------------------------------------------------------------
+// Parallel split writer.
+//
+// The same choice as SplitChooser, in three passes over a log the encoder keeps
+// (per word: the index of the symbol being encoded when it was emitted, so the
+// event's own index is that minus W, and the post-shift state):
+//  1. per chunk of words, each lane's latest event inside the chunk (threads);
+//     a prefix over the chunks gives each chunk the lanes' latest events before it;
+//  2. per chunk, Imin at every word (oldest of the lanes' latest events, a
+//     recency list started from the carried-in events) and the streaming
+//     candidate test (threads);
+//  3. the greedy choice of Def. 4.1, split by split. Imax grows strictly and Imin
+//     never falls from word to word, so with c = Imax_{k-1} + T the score
+//     H = |t - T| + |t - t_s - T| = |Imax - c| + |Imin - 1 - c| falls strictly
+//     while Imax < c, equals t_s while Imax >= c >= Imin - 1, and rises strictly
+//     once Imin - 1 > c; the window ends at the first candidate with
+//     Imin > c + T + 1 (t > 2T + t_s). Binary searches find those boundaries and
+//     only the last falling candidate, the level ones and the first rising one
+//     are scored, in word order with ties to the earlier word, as the streaming
+//     chooser scores the whole window. The chosen words' backward scans follow.
+// --------------------------------------------------------------------------
+std::atomic<uint32_t> g_split_threads{0};   // 0: automatic, 1: streaming chooser, >= 2: this many threads
+
+constexpr uint64_t kParallelSplitMinSymbols = 1ull << 24;
+// Per-word key of pass 2: Imin + 1 in bits 0..30 (0 before every lane has an event),
+// bit 31 set when the word is no candidate.
+constexpr uint32_t kNotCandidate = 0x80000000u;
+
+uint32_t split_writer_threads(uint64_t n_symbols) {
+    const uint32_t t = g_split_threads.load(std::memory_order_relaxed);
+    if (t) return t;
+    if (n_symbols < kParallelSplitMinSymbols) return 1;
+    return std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+}
+
+struct EventLog {
+    std::vector<uint32_t> sym;     // per word: index of the symbol being encoded
+    std::vector<uint16_t> state;   // per word: post-shift state
+};
+
+void choose_splits_parallel(BlobData &b, const EventLog &log, uint32_t M, uint32_t threads) {
+    const uint32_t W = b.lanes;
+    const uint64_t B = log.sym.size();
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(threads, B / 4096 + 1));
+    auto chunk_lo = [&](uint32_t c) { return B * c / chunks; };
+    auto run = [&](auto &&fn) {
+        std::vector<std::thread> ts;
+        for (uint32_t c = 1; c < chunks; ++c) ts.emplace_back(fn, c);
+        fn(0u);
+        for (std::thread &t : ts) t.join();
+    };
+    // Pass 1: each lane's latest event inside each chunk.
+    std::vector<int64_t> last((size_t)chunks * W, -1);
+    run([&](uint32_t c) {
+        int64_t *l = &last[(size_t)c * W];
+        for (uint64_t w = chunk_lo(c); w < chunk_lo(c + 1); ++w) {
+            const int64_t idx = (int64_t)log.sym[w] - (int64_t)W;
+            if (idx >= 0) l[(uint64_t)idx % W] = idx;
+        }
+    });
+    std::vector<int64_t> carry((size_t)chunks * W, -1);
+    for (uint32_t c = 1; c < chunks; ++c)
+        for (uint32_t j = 0; j < W; ++j) {
+            const int64_t v = last[(size_t)(c - 1) * W + j];
+            carry[(size_t)c * W + j] = v >= 0 ? v : carry[(size_t)(c - 1) * W + j];
+        }
+    // Pass 2: Imin at every word and the candidate test.
+    std::vector<uint32_t> key(B, 0);
+    run([&](uint32_t c) {
+        std::vector<int64_t> lst(carry.begin() + (size_t)c * W, carry.begin() + (size_t)(c + 1) * W);
+        std::vector<int32_t> prv(W, -1), nxt(W, -1), order;
+        int32_t head = -1, tail = -1;
+        uint32_t valid = 0;
+        for (uint32_t j = 0; j < W; ++j) if (lst[j] >= 0) order.push_back((int32_t)j);
+        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t z) { return lst[a] < lst[z]; });
+        auto append = [&](int32_t j) {
+            prv[j] = tail; nxt[j] = -1;
+            if (tail >= 0) nxt[tail] = j; else head = j;
+            tail = j;
+        };
+        auto unlink = [&](int32_t j) {
+            if (prv[j] >= 0) nxt[prv[j]] = nxt[j]; else head = nxt[j];
+            if (nxt[j] >= 0) prv[nxt[j]] = prv[j]; else tail = prv[j];
+        };
+        for (int32_t j : order) { append(j); ++valid; }
+        for (uint64_t w = chunk_lo(c); w < chunk_lo(c + 1); ++w) {
+            const int64_t idx = (int64_t)log.sym[w] - (int64_t)W;
+            if (idx >= 0) {
+                const int32_t j = (int32_t)((uint64_t)idx % W);
+                if (lst[j] < 0) ++valid; else unlink(j);
+                append(j);
+                lst[j] = idx;
+            }
+            const int64_t imin = valid == W ? lst[head] : -1;
+            const bool cand = idx >= 0 && valid == W && (uint64_t)(idx / W - imin / W) <= kMaxGroupDiff;
+            key[w] = (uint32_t)(imin + 1) | (cand ? 0u : kNotCandidate);
+        }
+    });
+    // Pass 3: the greedy choice (Def. 4.1) and the chosen words' backward scans.
+    uint32_t k = 1;
+    int64_t prev_max = -1, T = 0;
+    auto retarget = [&] {
+        const int64_t remaining = std::max<int64_t>(0, (int64_t)b.n_symbols - prev_max - 1);
+        T = (int64_t)cdiv((uint64_t)remaining, M - k + 1);
+    };
+    retarget();
+    std::vector<int64_t> snap_idx(W, -1), idx_of(W);
+    std::vector<uint16_t> snap_state(W, 0);
+    std::vector<uint8_t> seen(W);
+    uint64_t floor = 0;   // first word after the previous chosen one
+    auto imax_of = [&](uint64_t w) { return (int64_t)log.sym[w] - (int64_t)W; };
+    auto imin_of = [&](uint64_t w) { return (int64_t)(key[w] & ~kNotCandidate) - 1; };
+    auto is_cand = [&](uint64_t w) { return !(key[w] & kNotCandidate); };
+    // First word in [lo, B) whose Imin exceeds v (Imin never falls), or B.
+    auto first_imin_above = [&](uint64_t lo, int64_t v) {
+        uint64_t l = lo, h = B;
+        while (l < h) { const uint64_t m = l + (h - l) / 2; if (imin_of(m) > v) h = m; else l = m + 1; }
+        return l;
+    };
+    // First word in [lo, B) whose Imax is at least v (Imax grows), or B.
+    auto first_imax_from = [&](uint64_t lo, int64_t v) {
+        uint64_t l = lo, h = B;
+        while (l < h) { const uint64_t m = l + (h - l) / 2; if (imax_of(m) >= v) h = m; else l = m + 1; }
+        return l;
+    };
+    auto choose = [&](uint64_t wb) {
+        const int64_t imax = imax_of(wb);
+        std::fill(seen.begin(), seen.end(), 0);
+        const size_t base = b.sp_state.size();
+        b.sp_state.resize(base + W);
+        b.sp_gdiff.resize(base + W);
+        uint32_t nseen = 0;
+        for (uint64_t q = wb + 1; q > floor && nseen < W; --q) {
+            const int64_t idx = imax_of(q - 1);
+            if (idx < 0) continue;
+            const uint32_t j = (uint32_t)((uint64_t)idx % W);
+            if (seen[j]) continue;
+            seen[j] = 1;
+            ++nseen;
+            idx_of[j] = idx;
+            b.sp_state[base + j] = log.state[q - 1];
+        }
+        for (uint32_t j = 0; j < W; ++j) {
+            if (!seen[j]) { idx_of[j] = snap_idx[j]; b.sp_state[base + j] = snap_state[j]; }
+            snap_idx[j] = idx_of[j];
+            snap_state[j] = b.sp_state[base + j];
+        }
+        const uint64_t anchor = (uint64_t)imax / W;
+        for (uint32_t j = 0; j < W; ++j) b.sp_gdiff[base + j] = (uint16_t)(anchor - (uint64_t)idx_of[j] / W);
+        b.sp_next.push_back(wb + 1);
+        b.sp_anchor.push_back(anchor);
+        floor = wb + 1;
+        prev_max = imax;
+        ++k;
+        retarget();
+    };
+    while (k < M) {
+        uint64_t lo = floor;
+        while (lo < B && !is_cand(lo)) ++lo;
+        if (lo >= B) break;
+        const int64_t c = prev_max + T;
+        // The window: candidates before the first one with t > 2T + t_s.
+        uint64_t end = first_imin_above(lo, c + T + 1);
+        while (end < B && !is_cand(end)) ++end;
+        if (end == lo) { choose(lo); continue; }   // the first candidate already closes it
+        bool have = false;
+        uint64_t best = 0;
+        int64_t best_h = 0;
+        auto score = [&](uint64_t w) {
+            const int64_t t = imax_of(w) - prev_max, ts = imax_of(w) - imin_of(w) + 1;
+            const int64_t h = std::llabs(t - T) + std::llabs(t - ts - T);
+            if (!have || h < best_h) { have = true; best = w; best_h = h; }
+        };
+        const uint64_t a_end = std::min(end, first_imax_from(lo, c));
+        const uint64_t c_start = std::max(a_end, std::min(end, first_imin_above(lo, c + 1)));
+        for (uint64_t w = a_end; w > lo; --w)
+            if (is_cand(w - 1)) { score(w - 1); break; }    // the last falling candidate
+        for (uint64_t w = a_end; w < c_start; ++w)
+            if (is_cand(w)) score(w);                       // the level ones
+        for (uint64_t w = c_start; w < end; ++w)
+            if (is_cand(w)) { score(w); break; }            // the first rising one
+        choose(best);
+    }
+}
+
 // tidx: adaptive coding (symbol i with table tidx[i]), or NULL for the one table.
 template <typename Sym>
 void encode_stream(const Sym *sym, BlobData &b, uint32_t threads, const uint8_t *tidx = nullptr) {
@@ -290,6 +477,13 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads, const uint8_t 
         for (uint32_t s = 0; s < A; ++s) F[(size_t)t * (A + 1) + s + 1] = F[(size_t)t * (A + 1) + s] + b.freq[(size_t)t * A + s];
     SplitChooser chooser(b, threads);
     const bool want_splits = threads > 1;
+    // The threaded writer keeps symbol indices and Imin + 1 in 31 bits.
+    const uint32_t writers = want_splits && b.n_symbols < (1ull << 31) ? split_writer_threads(b.n_symbols) : 1u;
+    EventLog log;
+    if (writers > 1) {
+        log.sym.reserve((size_t)(b.n_symbols / 2) + 16);
+        log.state.reserve((size_t)(b.n_symbols / 2) + 16);
+    }
     uint32_t x[64];
     for (uint32_t j = 0; j < W; ++j) x[j] = kLower;
     std::vector<uint16_t> &words = *b.words_buf;
@@ -306,13 +500,18 @@ void encode_stream(const Sym *sym, BlobData &b, uint32_t threads, const uint8_t 
             // Emit the low word first, then shift (Eq. 3).
             words.push_back((uint16_t)(xs & 0xFFFFu));
             xs >>= kWordBits;
-            if (want_splits)
+            if (writers > 1) {
+                log.sym.push_back((uint32_t)i);
+                log.state.push_back((uint16_t)xs);
+            } else if (want_splits) {
                 chooser.event(words.size() - 1, (int64_t)i - (int64_t)W, xs);
+            }
         }
         x[j] = ((xs / fs) << n) + F[(size_t)t * (A + 1) + s] + (xs % fs);     // Eq. 1
         if (++j == W) j = 0;
     }
-    if (want_splits) chooser.finish();
+    if (writers > 1) choose_splits_parallel(b, log, threads, writers);
+    else if (want_splits) chooser.finish();
     b.final_states.assign(x, x + W);
 }
 
@@ -859,6 +1058,10 @@ recoil_status recoil_encode_adaptive(const void *symbols, uint64_t n_symbols, co
 recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                                         const uint32_t *freq, uint32_t partitions, recoil_blob **out) {
     return recoil::encode_partitioned(symbols, n_symbols, cfg, freq, partitions, out);
+}
+
+void recoil_set_split_writer_threads(uint32_t threads) {
+    recoil::g_split_threads.store(threads, std::memory_order_relaxed);
 }
 
 recoil_status recoil_combine_splits(const recoil_blob *in, uint32_t target_splits, recoil_blob **out) {

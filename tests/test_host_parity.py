@@ -293,3 +293,71 @@ def test_wide_limits(rc):
     from paper_2306_12141_amd import batch
     with pytest.raises(rc.RecoilError, match="unsupported"):
         batch.Batch([ok])
+
+
+SPLIT_WRITER_CASES = [
+    # lanes, n, dtype, alphabet, N, splits, zipf
+    (32, 11, np.uint8, 256, 300_001, 64, 1.1),
+    (64, 12, np.uint8, 256, 200_000, 37, 0.9),
+    (1, 8, np.uint8, 16, 5_000, 12, 1.0),
+    (3, 10, np.uint8, 100, 20_000, 17, None),
+    (17, 16, np.uint8, 256, 50_000, 9, 1.4),
+    (32, 12, np.uint16, 4096, 100_000, 20, 1.2),
+    (32, 11, np.uint8, 256, 10, 4, None),
+    (32, 12, np.uint8, 2, 100_000, 100, 4.0),
+    (64, 4, np.uint8, 3, 30_000, 1000, 0.5),
+    (32, 11, np.uint8, 256, 1 << 20, 30_000, 1.1),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(SPLIT_WRITER_CASES)))
+def test_parallel_split_writer_identical(rc, orc, ci):
+    """The threaded split writer (segmented per-lane scan, then the greedy walk)
+    chooses the streaming chooser's split points: containers byte-identical for
+    2, 3 and 8 threads, and equal to the oracle's."""
+    W, n, dt, A, N, M, z = SPLIT_WRITER_CASES[ci]
+    s = _syms(9000 + ci, N, A, dt, z)
+    outs = []
+    try:
+        for t in (1, 2, 3, 8):
+            rc.set_split_writer_threads(t)
+            outs.append(rc.encode(s, lanes=W, quant_bits=n, splits=M, alphabet=A).to_bytes())
+    finally:
+        rc.set_split_writer_threads(0)
+    assert all(o == outs[0] for o in outs[1:])
+    if N <= 300_001:
+        p = orc.params(lanes=W, quant_bits=n, symbol_bytes=np.dtype(dt).itemsize, alphabet=A)
+        assert outs[0] == orc.encode(s, p, M).container()
+
+
+def test_parallel_split_writer_adaptive(rc, orc):
+    pmfs, tidx, s = synth.adaptive_stream(9100, 400_000, 8, 64)
+    tabs = np.stack([orc.quantize((pmf * (1 << 30)).astype(np.uint64) + 1, 10) for pmf in pmfs])
+    outs = []
+    try:
+        for t in (1, 4):
+            rc.set_split_writer_threads(t)
+            outs.append(rc.encode_adaptive(s, tabs, tidx, lanes=32, quant_bits=10, splits=300, alphabet=64).to_bytes())
+    finally:
+        rc.set_split_writer_threads(0)
+    assert outs[0] == outs[1]
+
+
+def test_parallel_split_writer_sparse_events(rc):
+    """Words so rare that most positions fail the 16-bit group-difference test
+    (f = 2^16 - 1 for symbol 0 at n = 16): the threaded writer still chooses the
+    streaming chooser's split points, including when fewer than M exist."""
+    N = 1 << 21
+    s = np.zeros(N, dtype=np.uint8)
+    s[(synth.splitmix64(9200, 0, 64) % np.uint64(N)).astype(np.int64)] = 1
+    freq = np.array([65535, 1], dtype=np.uint32)
+    outs = []
+    try:
+        for t in (1, 2, 8):
+            rc.set_split_writer_threads(t)
+            for W, M in ((2, 8), (32, 64)):
+                outs.append((t, W, rc.encode(s, lanes=W, quant_bits=16, splits=M, alphabet=2, freq=freq).to_bytes()))
+    finally:
+        rc.set_split_writer_threads(0)
+    ref = {W: o for t, W, o in outs if t == 1}
+    assert all(o == ref[W] for t, W, o in outs)
