@@ -512,3 +512,24 @@ def test_wide_full_size(rc, W):
     _say("case wide full", W)
     blob = rc.encode(s, lanes=W, quant_bits=16, splits=spec.splits)
     assert np.array_equal(gpu_decode(rc, blob), s)
+
+
+def test_wide_partitioned_and_packed(rc):
+    """n = 16 with the other plan kinds: conventional sub-sequences decoded through the
+    two-level table, and a packed plan (records unpacked on the device)."""
+    s = _syms(6100, 1_000_003, 256, np.uint8, 1.1)
+    _say("case wide partitioned / packed")
+    part = rc.encode_partitioned(s, lanes=32, quant_bits=16, partitions=300)
+    assert np.array_equal(gpu_decode(rc, part), s)
+    blob = rc.encode(s, lanes=64, quant_bits=16, splits=200)
+    for t in (0, 50):
+        plan = rc.Plan(blob, packed_target=t)
+        ws = plan.allocate_workspace()
+        plan.upload(ws)
+        out = plan.allocate_output()
+        out.fill_(0xA5)
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        plan.decode(ws, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0
+        assert np.array_equal(plan.symbols_of(out), s), f"packed target {t}"
