@@ -83,6 +83,7 @@ enum {
     RECOIL_ERR_ALIGNMENT = -7,      /* a device pointer is not aligned as required */
     RECOIL_ERR_BUSY = -8,           /* serving: request refused by admission control */
     RECOIL_ERR_NOT_FOUND = -9,
+    RECOIL_ERR_OUT_OF_MEMORY = -10, /* host memory or threads could not be obtained */
 };
 
 /* Device error word bits (set with atomic OR by the decode kernels). */

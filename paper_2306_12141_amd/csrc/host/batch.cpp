@@ -2,6 +2,7 @@
 // layout, the persistent launch, the one-launch-per-stream baseline, HIP graph
 // capture and the autotuner.
 #include <algorithm>
+#include <memory>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -159,21 +160,22 @@ recoil_tuning recoil_default_tuning(void) { return recoil_tuning{16, 4, 2, 0, 0}
 
 recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t count, const recoil_tuning *tuning,
                                   recoil_batch **out, size_t *workspace_bytes, size_t *output_bytes) {
+    return recoil::guarded("batch_create", [&]() -> recoil_status {
     using namespace recoil;
     if (!blobs || !out || count == 0) return fail(RECOIL_ERR_INVALID_ARG, "batch_create: bad arguments");
     *out = nullptr;
-    auto *h = new (std::nothrow) recoil_batch();
-    if (!h) return fail(RECOIL_ERR_INVALID_ARG, "batch_create: out of memory");
+    std::unique_ptr<recoil_batch> hp(new recoil_batch());
+    recoil_batch *h = hp.get();
     BatchData &b = h->d;
     b.tuning = tuning ? *tuning : recoil_default_tuning();
-    if (!tuning_ok(b.tuning)) { delete h; return fail(RECOIL_ERR_INVALID_ARG, "batch_create: unsupported tuning"); }
+    if (!tuning_ok(b.tuning)) { return fail(RECOIL_ERR_INVALID_ARG, "batch_create: unsupported tuning"); }
     b.plans.resize(count);
     for (uint32_t i = 0; i < count; ++i) {
-        if (!blobs[i]) { delete h; return fail(RECOIL_ERR_INVALID_ARG, "batch_create: NULL blob"); }
-        if (blobs[i]->data->adaptive) { delete h; return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: adaptive streams are decoded alone"); }
-        if (blobs[i]->data->quant_bits > 12) { delete h; return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: n > 12 streams are decoded alone"); }
+        if (!blobs[i]) { return fail(RECOIL_ERR_INVALID_ARG, "batch_create: NULL blob"); }
+        if (blobs[i]->data->adaptive) { return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: adaptive streams are decoded alone"); }
+        if (blobs[i]->data->quant_bits > 12) { return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: n > 12 streams are decoded alone"); }
         recoil_status st = build_plan(blobs[i]->data, b.plans[i]);
-        if (st) { delete h; return st; }
+        if (st) { return st; }
         b.lut_bytes = std::max<uint32_t>(b.lut_bytes, (uint32_t)b.plans[i].lut.size());
     }
     // Item capacity: the finest tuning (8 waves, one pair per wave).
@@ -213,11 +215,12 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     b.total_ws = off;
     b.total_out = std::max<size_t>(out_off, 256);
     build_items(b);
-    if (b.items.size() > b.items_cap) { delete h; return fail(RECOIL_ERR_INVALID_ARG, "batch_create: too many items"); }
+    if (b.items.size() > b.items_cap) { return fail(RECOIL_ERR_INVALID_ARG, "batch_create: too many items"); }
     if (workspace_bytes) *workspace_bytes = b.total_ws;
     if (output_bytes) *output_bytes = b.total_out;
-    *out = h;
+    *out = hp.release();
     return RECOIL_OK;
+    });
 }
 
 void recoil_batch_free(recoil_batch *batch) { delete batch; }
@@ -243,6 +246,7 @@ static recoil_status upload_items(const recoil::BatchData &b, void *d_ws, hipStr
 }
 
 recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t bytes, hipStream_t stream) {
+    return recoil::guarded("batch_upload", [&]() -> recoil_status {
     using namespace recoil;
     if (!batch || !d_ws) return fail(RECOIL_ERR_INVALID_ARG, "batch_upload: bad arguments");
     const BatchData &b = batch->d;
@@ -267,6 +271,7 @@ recoil_status recoil_batch_upload(const recoil_batch *batch, void *d_ws, size_t 
     }
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("batch_upload: ") + hipGetErrorString(e));
     return upload_items(b, d_ws, stream);
+    });
 }
 
 recoil_status recoil_batch_set_tuning(recoil_batch *batch, const recoil_tuning *t, void *d_ws, hipStream_t stream) {

@@ -3,6 +3,8 @@
 
 #include <cstdint>
 #include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -74,6 +76,21 @@ std::shared_ptr<BlobData> combine_data(const BlobData &a, uint32_t target);
 
 void set_error(const std::string &msg);
 recoil_status fail(recoil_status s, const std::string &msg);
+
+// Runs an entry point's body: host allocation or thread-creation failures inside it
+// come back as RECOIL_ERR_OUT_OF_MEMORY instead of crossing the C boundary.
+template <typename F>
+recoil_status guarded(const char *what, F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(RECOIL_ERR_OUT_OF_MEMORY, std::string(what) + ": out of host memory");
+    } catch (const std::exception &e) {
+        return fail(RECOIL_ERR_OUT_OF_MEMORY, std::string(what) + ": " + e.what());
+    } catch (...) {
+        return fail(RECOIL_ERR_OUT_OF_MEMORY, std::string(what) + ": host resources exhausted");
+    }
+}
 
 }  // namespace recoil
 

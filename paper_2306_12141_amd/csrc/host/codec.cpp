@@ -1033,6 +1033,7 @@ const char *recoil_status_string(recoil_status s) {
     case RECOIL_ERR_ALIGNMENT: return "misaligned pointer";
     case RECOIL_ERR_BUSY: return "busy";
     case RECOIL_ERR_NOT_FOUND: return "not found";
+    case RECOIL_ERR_OUT_OF_MEMORY: return "out of host memory";
     default: return "unknown status";
     }
 }
@@ -1041,23 +1042,31 @@ const char *recoil_last_error(void) { return recoil::g_last_error.c_str(); }
 const char *recoil_version(void) { return "librecoil 0.1 (gfx950)"; }
 
 recoil_status recoil_quantize(const uint64_t *counts, uint32_t alphabet, uint32_t quant_bits, uint32_t *f_out) {
+    return recoil::guarded("quantize", [&]() -> recoil_status {
     return recoil::quantize(counts, alphabet, quant_bits, f_out);
+    });
 }
 
 recoil_status recoil_encode(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                             const uint32_t *freq, uint32_t n_splits, recoil_blob **out) {
+    return recoil::guarded("encode", [&]() -> recoil_status {
     return recoil::encode(symbols, n_symbols, cfg, freq, n_splits, out);
+    });
 }
 
 recoil_status recoil_encode_adaptive(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                                      const uint32_t *freqs, uint32_t tables, const uint8_t *table_index,
                                      uint32_t n_splits, recoil_blob **out) {
+    return recoil::guarded("encode_adaptive", [&]() -> recoil_status {
     return recoil::encode_adaptive(symbols, n_symbols, cfg, freqs, tables, table_index, n_splits, out);
+    });
 }
 
 recoil_status recoil_encode_partitioned(const void *symbols, uint64_t n_symbols, const recoil_config *cfg,
                                         const uint32_t *freq, uint32_t partitions, recoil_blob **out) {
+    return recoil::guarded("encode_partitioned", [&]() -> recoil_status {
     return recoil::encode_partitioned(symbols, n_symbols, cfg, freq, partitions, out);
+    });
 }
 
 void recoil_set_split_writer_threads(uint32_t threads) {
@@ -1065,15 +1074,21 @@ void recoil_set_split_writer_threads(uint32_t threads) {
 }
 
 recoil_status recoil_combine_splits(const recoil_blob *in, uint32_t target_splits, recoil_blob **out) {
+    return recoil::guarded("combine_splits", [&]() -> recoil_status {
     return recoil::combine(in, target_splits, out);
+    });
 }
 
 recoil_status recoil_blob_serialize(const recoil_blob *blob, void *dst, size_t cap, size_t *written) {
+    return recoil::guarded("blob_serialize", [&]() -> recoil_status {
     return recoil::serialize(blob, dst, cap, written);
+    });
 }
 
 recoil_status recoil_blob_deserialize(const void *src, size_t len, recoil_blob **out) {
+    return recoil::guarded("blob_deserialize", [&]() -> recoil_status {
     return recoil::deserialize(src, len, out);
+    });
 }
 
 recoil_status recoil_blob_info(const recoil_blob *blob, recoil_blob_info_t *out) {

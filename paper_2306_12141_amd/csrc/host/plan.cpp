@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -306,30 +307,32 @@ hipError_t enqueue_unpack(const recoil::PlanData &pl, char *base, hipStream_t st
 extern "C" {
 
 recoil_status recoil_plan_create(const recoil_blob *blob, recoil_plan **out, size_t *device_bytes) {
+    return recoil::guarded("plan_create", [&]() -> recoil_status {
     using namespace recoil;
     if (!blob || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_create: bad arguments");
     *out = nullptr;
-    auto *p = new (std::nothrow) recoil_plan();
-    if (!p) return fail(RECOIL_ERR_INVALID_ARG, "plan_create: out of memory");
+    std::unique_ptr<recoil_plan> p(new recoil_plan());
     recoil_status st = build_plan(blob->data, p->d);
-    if (st) { delete p; return st; }
+    if (st) return st;
     if (device_bytes) *device_bytes = p->d.total;
-    *out = p;
+    *out = p.release();
     return RECOIL_OK;
+    });
 }
 
 recoil_status recoil_plan_create_packed(const recoil_blob *blob, uint32_t target_units, recoil_plan **out,
                                         size_t *device_bytes) {
+    return recoil::guarded("plan_create_packed", [&]() -> recoil_status {
     using namespace recoil;
     if (!blob || !out) return fail(RECOIL_ERR_INVALID_ARG, "plan_create_packed: bad arguments");
     *out = nullptr;
-    auto *p = new (std::nothrow) recoil_plan();
-    if (!p) return fail(RECOIL_ERR_INVALID_ARG, "plan_create_packed: out of memory");
+    std::unique_ptr<recoil_plan> p(new recoil_plan());
     recoil_status st = build_plan_packed(blob->data, target_units, p->d);
-    if (st) { delete p; return st; }
+    if (st) return st;
     if (device_bytes) *device_bytes = p->d.total;
-    *out = p;
+    *out = p.release();
     return RECOIL_OK;
+    });
 }
 
 size_t recoil_plan_metadata_device_bytes(const recoil_plan *plan) {
@@ -360,6 +363,7 @@ recoil_status recoil_plan_get_layout(const recoil_plan *plan, recoil_plan_layout
 }
 
 recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t bytes, hipStream_t stream) {
+    return recoil::guarded("plan_upload", [&]() -> recoil_status {
     using namespace recoil;
     if (!plan || !d_ws) return fail(RECOIL_ERR_INVALID_ARG, "plan_upload: bad arguments");
     const PlanData &pl = plan->d;
@@ -384,6 +388,7 @@ recoil_status recoil_plan_upload(const recoil_plan *plan, void *d_ws, size_t byt
     }
     if (e != hipSuccess) return fail(RECOIL_ERR_HIP, std::string("plan_upload: ") + hipGetErrorString(e));
     return RECOIL_OK;
+    });
 }
 
 recoil_status recoil_plan_unpack(const recoil_plan *plan, void *d_ws, hipStream_t stream) {

@@ -532,6 +532,7 @@ uint64_t recoil_server_now_ns(void) { return recoil::clock_ns(); }
 
 recoil_status recoil_server_create(const recoil_server_config *cfg, void *d_arena, size_t arena_bytes,
                                    recoil_server **out) {
+    return recoil::guarded("server_create", [&]() -> recoil_status {
     using namespace recoil;
     if (!cfg || !d_arena || !out) return fail(RECOIL_ERR_INVALID_ARG, "server_create: bad arguments");
     *out = nullptr;
@@ -579,13 +580,28 @@ recoil_status recoil_server_create(const recoil_server_config *cfg, void *d_aren
         delete s;
         return fail(RECOIL_ERR_HIP, std::string("server_create: ") + hipGetErrorString(e));
     }
-    for (uint32_t i = 0; i < cfg->prep_threads; ++i) s->preppers.emplace_back(prep_loop, s);
-    s->launcher = std::thread(launcher_loop, s);
+    try {
+        for (uint32_t i = 0; i < cfg->prep_threads; ++i) s->preppers.emplace_back(prep_loop, s);
+        s->launcher = std::thread(launcher_loop, s);
+    } catch (...) {
+        // A thread could not be started: stop the ones that were, then report.
+        {
+            std::lock_guard<std::mutex> lk(s->prep_mu);
+            s->prep_stop = true;
+        }
+        s->cv_prep.notify_all();
+        for (std::thread &t : s->preppers) t.join();
+        destroy_slots(s);
+        delete s;
+        throw;
+    }
     *out = s;
     return RECOIL_OK;
+    });
 }
 
 recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blob, uint32_t *content_id) {
+    return recoil::guarded("server_add_content", [&]() -> recoil_status {
     using namespace recoil;
     if (!s || !blob || !content_id) return fail(RECOIL_ERR_INVALID_ARG, "server_add_content: bad arguments");
     const std::shared_ptr<const BlobData> &bp = blob->data;
@@ -623,10 +639,12 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
     *content_id = (uint32_t)s->contents.size();
     s->contents.push_back(std::move(ct));
     return RECOIL_OK;
+    });
 }
 
 recoil_status recoil_server_submit(recoil_server *s, uint32_t content, uint32_t splits, uint64_t tag,
                                    uint64_t arrival_ns, uint64_t *request_id) {
+    return recoil::guarded("server_submit", [&]() -> recoil_status {
     using namespace recoil;
     if (!s) return fail(RECOIL_ERR_INVALID_ARG, "server_submit: NULL server");
     auto r = std::make_shared<Request>();
@@ -653,6 +671,7 @@ recoil_status recoil_server_submit(recoil_server *s, uint32_t content, uint32_t 
     }
     s->cv_prep.notify_one();
     return RECOIL_OK;
+    });
 }
 
 uint32_t recoil_server_poll(recoil_server *s, recoil_completion *done, uint32_t cap, uint32_t timeout_us) {
