@@ -533,3 +533,14 @@ def test_wide_partitioned_and_packed(rc):
         torch.cuda.synchronize()
         assert int(err.item()) == 0
         assert np.array_equal(plan.symbols_of(out), s), f"packed target {t}"
+
+
+def test_above_2gib_output(rc):
+    """The largest outputs: 2^31 + 4099 uint8 symbols (output offsets and symbol
+    indices past 2^31), W = 64, 65536 units, the default launch shape."""
+    N = (1 << 31) + 4099
+    s = synth.draw_symbols(synth.zipf_pmf(256, 1.1), 6200, N, np.uint8)
+    _say("case 2 GiB + 4099 symbols")
+    blob = rc.encode(s, lanes=64, quant_bits=12, splits=65536)
+    assert blob.info.n_words < (1 << 31) - 1024
+    assert np.array_equal(gpu_decode(rc, blob), s)
