@@ -253,3 +253,23 @@ def test_batch_with_partitioned_streams(rc, mixed):
         torch.cuda.synchronize()
         assert int(err.item()) == 0
         _check_all(batch, out, streams)
+
+
+def test_batch_offsets_past_2gib(rc, mixed):
+    """A batch whose outputs end past 2^31 bytes: a 2 GiB + 77-symbol stream first,
+    then the mixed streams, so their output offsets exceed 2^31."""
+    from paper_2306_12141_amd.batch import Batch
+    import synth
+    N = (1 << 31) + 77
+    big = synth.draw_symbols(synth.zipf_pmf(256, 1.1), 6300, N, np.uint8)
+    _say("batch with a 2 GiB stream")
+    streams = [(big, rc.encode(big, lanes=32, quant_bits=11, splits=32768))] + list(mixed[:8])
+    batch = Batch([b for _, b in streams])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    out.fill_(0xEE)
+    batch.decode(ws, out, err)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    assert batch.output_range(len(streams) - 1)[0] > (1 << 31)
+    _check_all(batch, out, streams)
