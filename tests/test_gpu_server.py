@@ -217,3 +217,25 @@ def test_full_size_requests(rc, big_corpus):
         assert srv.stats().budget_used == 0
     finally:
         srv.close()
+
+
+def test_add_content_refuses_streams_decoded_alone(rc, corpus):
+    """Conventional partitioned, adaptive and n > 12 streams are refused at
+    add_content with RECOIL_ERR_UNSUPPORTED; the server keeps serving."""
+    srv, ids = _server(rc, corpus, 16 << 20)
+    try:
+        s = synth.draw_symbols(synth.zipf_pmf(256, 1.1), 6400, 100_000, np.uint8)
+        pmfs, tidx, sa = synth.adaptive_stream(6401, 100_000, 4, 64)
+        tabs = np.stack([rc.quantize((pmf * (1 << 30)).astype(np.uint64) + 1, 10) for pmf in pmfs])
+        refused = [rc.encode_partitioned(s, lanes=32, quant_bits=11, partitions=8),
+                   rc.encode_adaptive(sa, tabs, tidx, lanes=32, quant_bits=10, splits=16, alphabet=64),
+                   rc.encode(s, lanes=32, quant_bits=16, splits=16)]
+        for b in refused:
+            with pytest.raises(rc.RecoilError) as e:
+                srv.add_content(b)
+            assert e.value.status == -4
+        rid = srv.submit(ids[0], 3, tag=0)
+        _check(srv, corpus, _drain(srv, 1)[rid])
+        srv.release(rid)
+    finally:
+        srv.close()
