@@ -27,8 +27,9 @@ recoil_tuning recoil_default_tuning(void);
  * workspace size (words, tables, unit records, stream descriptors, work items,
  * queue counter) and the output size: stream i's symbols land at the offset given
  * by recoil_batch_output_offset (256-byte aligned). tuning: NULL for the default.
- * Errors: INVALID_ARG, UNSUPPORTED (see recoil_plan_create; also n > 12 and adaptive
- * streams, which are decoded alone).
+ * Streams with 13 <= n <= 16 (two-level tables) form a table class decoded by a
+ * launch of its own. Errors: INVALID_ARG, UNSUPPORTED (see recoil_plan_create; also
+ * adaptive streams, which are decoded alone).
  */
 recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t count, const recoil_tuning *tuning,
                                   recoil_batch **out, size_t *workspace_bytes, size_t *output_bytes);
@@ -59,8 +60,8 @@ recoil_status recoil_decode_batch(const recoil_batch *batch, void *d_workspace, 
  * For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): recoil_decode_batch with
  * the queue heads in a statically allocated device array of the library instead
- * of the workspace, so d_workspace is only read. The array is 256 bytes per GPU
- * (one head per table class, 128 bytes apart), held by every GPU the library runs
+ * of the workspace, so d_workspace is only read. The array is 384 bytes per GPU
+ * (one head for each of the three table classes, 128 bytes apart), held by every GPU the library runs
  * on until the process ends; each launch's head is reset by a kernel, not a
  * memset. The first call on a device looks up the array's address on that device
  * (hipGetSymbolAddress, current device), so make it outside graph capture. Calls

@@ -25,16 +25,18 @@ namespace {
 
 using namespace dev;
 
-template <int W, typename Sym, int K, int SS = 64 / W>
+template <int W, typename Sym, int K, int SS = 64 / W, int VAR = kPlain>
 __device__ inline void run_item(const DecodeParams &p, uint32_t lut, uint32_t ring0,
                                 uint32_t lane, uint32_t wave, uint32_t waves, uint32_t first, uint32_t count) {
-    PairDecoder<W, Sym, K, SS> d(p, lut, ring0, lane);
+    PairDecoder<W, Sym, K, SS, VAR> d(p, lut, ring0, lane);
     const uint32_t share = wave < count ? (count - 1 - wave) / waves + 1 : 0u;
     uint32_t left = share;
     for (uint32_t q = first + wave; q < first + count; q += waves) d.run(q, --left, share);
 }
 
-template <int K, int WAVES>
+// VAR: kPlain (one-level tables, n <= 12) or kWide (two-level, 13 <= n <= 16), one
+// kernel each so that the wide decode does not weigh on the common one's registers.
+template <int K, int WAVES, int VAR = kPlain>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_SGPR_BUDGET), amdgpu_waves_per_eu(8, 8))) void decode_batch(
     BatchParams bp) {
     using L = Lds<16, K, WAVES>;
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         const WorkItem wi = uni_load(bp.items + it);
         const StreamDesc d = uni_load(bp.streams + wi.stream);
         if ((int32_t)wi.stream != cur) {
-            const uint32_t chunks = ((d.symbol_bytes == 1 ? 4u : 8u) << d.quant_bits) / 16;
+            const uint32_t chunks = d.lut_chunks;
             const uint4 *src = reinterpret_cast<const uint4 *>(bp.ws + d.lut_off);
             for (uint32_t i = threadIdx.x; i < chunks; i += 64 * WAVES) reinterpret_cast<uint4 *>(lut)[i] = src[i];
             cur = (int32_t)wi.stream;
@@ -87,17 +89,17 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_num_sgpr(RECOIL_S
         } else if (d.lanes == 32) {
             if (single) {
                 if (lane < 32) {   // one unit per wave: the upper half-wave idles until the item ends
-                    if (d.symbol_bytes == 1) run_item<32, uint8_t, K, 1>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
-                    else run_item<32, uint16_t, K, 1>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                    if (d.symbol_bytes == 1) run_item<32, uint8_t, K, 1, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                    else run_item<32, uint16_t, K, 1, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
                 }
             } else if (d.symbol_bytes == 1) {
-                run_item<32, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                run_item<32, uint8_t, K, 2, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
             } else {
-                run_item<32, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+                run_item<32, uint16_t, K, 2, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
             }
         } else {
-            if (d.symbol_bytes == 1) run_item<64, uint8_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
-            else run_item<64, uint16_t, K>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            if (d.symbol_bytes == 1) run_item<64, uint8_t, K, 1, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
+            else run_item<64, uint16_t, K, 1, VAR>(p, base + L::TABLE, ring0, lane, wave, WAVES, wi.first, wi.count);
         }
         if (bp.remaining) {
             // Publish the stream's completion once its last item is done: every
@@ -126,26 +128,32 @@ size_t batch_lds(uint32_t lut_bytes) {
     return Lds<16, K, WAVES>::TABLE + lut_bytes;
 }
 
-template <int K, int WAVES>
+template <int K, int WAVES, int VAR = kPlain>
 int occupancy(uint32_t lut_bytes) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_batch<K, WAVES>, 64 * WAVES,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_batch<K, WAVES, VAR>, 64 * WAVES,
                                                      batch_lds<K, WAVES>(lut_bytes)) != hipSuccess)
         return 0;
     return per_cu;
 }
 
-template <int K, int WAVES>
-hipError_t launch(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t stream) {
+template <int K, int WAVES, int VAR>
+hipError_t launch_var(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t stream) {
     const int cus = device_cus();
-    int per_cu = occupancy<K, WAVES>(bp.lut_bytes);
+    int per_cu = occupancy<K, WAVES, VAR>(bp.lut_bytes);
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     if (blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)blocks_per_cu);
     const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(bp.n_items, (uint32_t)(cus * per_cu)));
     hipLaunchKernelGGL(reset_head, dim3(1), dim3(64), 0, stream, bp.head);
     const size_t lds = batch_lds<K, WAVES>(bp.lut_bytes);
-    hipLaunchKernelGGL((decode_batch<K, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, stream, bp);
+    hipLaunchKernelGGL((decode_batch<K, WAVES, VAR>), dim3(blocks), dim3(64 * WAVES), lds, stream, bp);
     return hipGetLastError();
+}
+
+template <int K, int WAVES>
+hipError_t launch(const BatchParams &bp, uint32_t blocks_per_cu, hipStream_t stream) {
+    return bp.wide ? launch_var<K, WAVES, kWide>(bp, blocks_per_cu, stream)
+                   : launch_var<K, WAVES, kPlain>(bp, blocks_per_cu, stream);
 }
 
 constexpr int kMaxDevices = 64;
@@ -182,7 +190,14 @@ hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t
     return hipErrorInvalidValue;
 }
 
-int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes) {
+int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes, bool wide) {
+    if (wide) {
+        if (t.chunk_groups == 4 && t.waves == 8) return occupancy<4, 8, kWide>(lut_bytes);
+        if (t.chunk_groups == 4 && t.waves == 16) return occupancy<4, 16, kWide>(lut_bytes);
+        if (t.chunk_groups == 8 && t.waves == 8) return occupancy<8, 8, kWide>(lut_bytes);
+        if (t.chunk_groups == 8 && t.waves == 16) return occupancy<8, 16, kWide>(lut_bytes);
+        return 0;
+    }
     if (t.chunk_groups == 4 && t.waves == 8) return occupancy<4, 8>(lut_bytes);
     if (t.chunk_groups == 4 && t.waves == 16) return occupancy<4, 16>(lut_bytes);
     if (t.chunk_groups == 8 && t.waves == 8) return occupancy<8, 8>(lut_bytes);

@@ -17,7 +17,8 @@ struct StreamDesc {
     uint32_t units;
     uint8_t quant_bits, symbol_bytes, lanes, single_symbol;
     uint32_t fill_symbol;
-    uint32_t partitioned;   // conventional sub-sequences (see DecodeParams::partitioned)
+    uint16_t partitioned;   // conventional sub-sequences (see DecodeParams::partitioned)
+    uint16_t lut_chunks;    // decode-table size in 16-byte chunks
 };
 static_assert(sizeof(StreamDesc) == 64, "StreamDesc is 64 bytes");
 
@@ -36,6 +37,7 @@ constexpr uint32_t kItemSingle = 0x80000000u;
 
 struct BatchParams {
     const unsigned char *ws;      // workspace base
+    uint32_t wide;                // nonzero: the two-level tables of 13 <= n <= 16 (a kernel of their own)
     unsigned char *out;           // output base
     const StreamDesc *streams;
     const WorkItem *items;
@@ -60,13 +62,14 @@ struct BatchTuning {
 
 // Statically allocated queue heads (recoil_decode_batch_noalloc): one device
 // array per GPU of kStaticScratchWords words, a head every kStaticHeadStride words.
-constexpr uint32_t kStaticScratchWords = 64, kStaticHeadStride = 32;
+constexpr uint32_t kStaticScratchWords = 96, kStaticHeadStride = 32;
 // Device address of that array on the current device, looked up once per device.
 hipError_t static_scratch(uint32_t **ptr);
 
 // Persistent batched launch: queue-head reset kernel + decode kernel on `stream`.
 hipError_t launch_batch(const BatchParams &bp, const BatchTuning &t, hipStream_t stream);
-// Occupancy-derived workgroups per CU for a tuning (0 if the tuning is not available).
-int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes);
+// Occupancy-derived workgroups per CU for a tuning (0 if the tuning is not available),
+// of the kernel for one-level tables or, with wide set, for two-level ones.
+int batch_blocks_per_cu(const BatchTuning &t, uint32_t lut_bytes, bool wide = false);
 
 }  // namespace recoil

@@ -17,17 +17,21 @@
 
 namespace recoil {
 
-// Streams are split into classes by decode-table size, each decoded by a launch of
-// its own whose LDS holds only its class's largest table: a 32 KiB uint16 table
-// would otherwise halve the resident waves of every uint8 stream's launch.
-constexpr uint32_t kBatchClasses = 2;
+// Streams are split into classes by decode table, each decoded by a launch of its
+// own whose LDS holds only its class's largest table: a 32 KiB uint16 table would
+// otherwise halve the resident waves of every uint8 stream's launch. Class 2 holds
+// the two-level tables of 13 <= n <= 16, decoded by a kernel of their own.
+constexpr uint32_t kBatchClasses = 3, kWideClass = 2;
 constexpr uint32_t kSmallTableBytes = 16384;   // class 0: tables up to 16 KiB (uint8, n <= 12)
-inline uint32_t table_class(size_t lut_bytes) { return lut_bytes <= kSmallTableBytes ? 0u : 1u; }
+inline uint32_t table_class(const PlanData &pl) {
+    if (pl.blob->quant_bits > 12) return kWideClass;
+    return pl.lut.size() <= kSmallTableBytes ? 0u : 1u;
+}
 
 struct BatchData {
     std::vector<PlanData> plans;
     std::vector<StreamDesc> descs;
-    std::vector<WorkItem> items;               // class 0's items, then class 1's
+    std::vector<WorkItem> items;               // class 0's items, then class 1's, then class 2's
     std::vector<uint64_t> out_off, out_bytes;
     size_t off_head = 0, off_descs = 0, off_items = 0, items_cap = 0, total_ws = 0, total_out = 0;
     uint32_t lut_bytes = 0;                    // largest table of the batch
@@ -40,7 +44,7 @@ namespace {
 
 // Head section of the batch workspace: one work-queue head per class (128 bytes
 // apart), each reset by a kernel before its class's persistent launch.
-constexpr size_t kBatchHeadBytes = 256, kHeadStride = 128;
+constexpr size_t kHeadStride = 128, kBatchHeadBytes = kBatchClasses * kHeadStride;
 
 // Units per run for a stream of M units under tuning value k (0 or 1: one).
 uint32_t run_of(uint32_t M, uint32_t k) { return std::max(1u, std::min(k, std::max(M, 1u))); }
@@ -70,7 +74,7 @@ void build_items(BatchData &b) {
     std::vector<uint32_t> order(b.plans.size());
     for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) {
-        const uint32_t ca = table_class(b.plans[a].lut.size()), cc = table_class(b.plans[c].lut.size());
+        const uint32_t ca = table_class(b.plans[a]), cc = table_class(b.plans[c]);
         if (ca != cc) return ca < cc;
         return b.plans[a].blob->n_symbols * b.plans[a].blob->symbol_bytes >
                b.plans[c].blob->n_symbols * b.plans[c].blob->symbol_bytes;
@@ -80,7 +84,7 @@ void build_items(BatchData &b) {
     for (uint32_t s : order) {
         const PlanData &pl = b.plans[s];
         if (pl.blob->n_symbols == 0) continue;
-        const uint32_t c = table_class(pl.lut.size());
+        const uint32_t c = table_class(pl);
         if (b.cls_count[c] == 0) b.cls_begin[c] = (uint32_t)b.items.size();
         b.cls_lut[c] = std::max<uint32_t>(b.cls_lut[c], (uint32_t)pl.lut.size());
         const size_t before = b.items.size();
@@ -118,6 +122,7 @@ BatchParams params_of(const BatchData &b, uint32_t cls, void *d_ws, void *d_out,
     bp.err = d_err;
     bp.n_items = b.cls_count[cls];
     bp.lut_bytes = b.cls_lut[cls];
+    bp.wide = cls == kWideClass ? 1u : 0u;
     return bp;
 }
 
@@ -134,7 +139,7 @@ hipError_t launch_classes(const BatchData &b, void *d_ws, void *d_out, uint32_t 
 // Launch shape fits the CU for every class that has work.
 bool shape_fits(const BatchData &b, const recoil_tuning &t) {
     for (uint32_t c = 0; c < kBatchClasses; ++c)
-        if (b.cls_count[c] && batch_blocks_per_cu(device_tuning(t), b.cls_lut[c]) < 1) return false;
+        if (b.cls_count[c] && batch_blocks_per_cu(device_tuning(t), b.cls_lut[c], c == kWideClass) < 1) return false;
     return true;
 }
 
@@ -173,7 +178,6 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
     for (uint32_t i = 0; i < count; ++i) {
         if (!blobs[i]) { return fail(RECOIL_ERR_INVALID_ARG, "batch_create: NULL blob"); }
         if (blobs[i]->data->adaptive) { return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: adaptive streams are decoded alone"); }
-        if (blobs[i]->data->quant_bits > 12) { return fail(RECOIL_ERR_UNSUPPORTED, "batch_create: n > 12 streams are decoded alone"); }
         recoil_status st = build_plan(blobs[i]->data, b.plans[i]);
         if (st) { return st; }
         b.lut_bytes = std::max<uint32_t>(b.lut_bytes, (uint32_t)b.plans[i].lut.size());
@@ -208,6 +212,7 @@ recoil_status recoil_batch_create(const recoil_blob *const *blobs, uint32_t coun
         d.single_symbol = pl.single_symbol ? 1 : 0;
         d.fill_symbol = pl.fill_symbol;
         d.partitioned = bd.partitioned() ? 1 : 0;
+        d.lut_chunks = (uint16_t)(pl.lut.size() / 16);
         b.out_off[i] = out_off;
         b.out_bytes[i] = bd.n_symbols * bd.symbol_bytes;
         out_off = ws_align(out_off + b.out_bytes[i]);

@@ -413,6 +413,7 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
         d.lanes = (uint8_t)b.lanes;
         d.single_symbol = ct.single_symbol ? 1 : 0;
         d.fill_symbol = ct.fill_symbol;
+        d.lut_chunks = (uint16_t)(ct.lut_bytes / 16);
         std::memcpy(meta + moff, r.plan.meta.data(), r.plan.meta.size() * sizeof(UnitMeta));
         std::memcpy(meta + moff + r.unit_bytes, r.plan.lanes.data(), r.plan.lanes.size() * 4);
         moff += r.meta_bytes;

@@ -273,3 +273,35 @@ def test_batch_offsets_past_2gib(rc, mixed):
     assert int(err.item()) == 0
     assert batch.output_range(len(streams) - 1)[0] > (1 << 31)
     _check_all(batch, out, streams)
+
+
+def test_batch_with_wide_tables(rc, mixed):
+    """Streams coded at 13 <= n <= 16 in a batch with one-level ones: three table
+    classes, the wide one decoded by its own kernel; persistent, per-stream, graph
+    replay and the allocation-free entry point all exact."""
+    from paper_2306_12141_amd.batch import Batch
+    import synth
+    wide = []
+    for i, (W, n, dt, A) in enumerate([(32, 16, np.uint8, 256), (64, 13, np.uint8, 256), (32, 15, np.uint16, 4096),
+                                       (64, 16, np.uint16, 1000), (32, 16, np.uint8, 256)]):
+        s = synth.draw_symbols(synth.zipf_pmf(A, 1.1), 6500 + i, 300_001 + 977 * i, dt)
+        wide.append((s, rc.encode(s, lanes=W, quant_bits=n, splits=40 + i, alphabet=A)))
+    streams = list(mixed[:12]) + wide
+    _say("batch with wide tables", len(streams))
+    batch = Batch([b for _, b in streams])
+    ws, out, err = batch.allocate()
+    batch.upload(ws)
+    for run in ("persistent", "per_stream", "graph", "noalloc"):
+        out.fill_(0x3C)
+        if run == "persistent":
+            batch.decode(ws, out, err)
+        elif run == "per_stream":
+            batch.decode_per_stream(ws, out, err)
+        elif run == "graph":
+            g = batch.graph(ws, out, err)
+            g.launch()
+        else:
+            batch.decode_noalloc(ws, out, err)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0, run
+        _check_all(batch, out, streams)
