@@ -98,9 +98,10 @@ recoil_status recoil_server_create(const recoil_server_config *cfg, void *d_aren
 /*
  * Make a blob servable: copies its words and decode table into the resident
  * region (synchronously) and keeps a reference to its split metadata. The blob
- * may be freed afterwards. Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n outside 8..12,
- * or a partitioned blob, whose units cannot be combined per request, or an adaptive or
- * n > 12 blob, which are decoded alone), BUFFER_TOO_SMALL
+ * may be freed afterwards. Errors: INVALID_ARG, UNSUPPORTED (W not 32/64, n outside 8..16,
+ * or a partitioned blob, whose units cannot be combined per request, or an adaptive
+ * blob, which is decoded alone; 13 <= n <= 16 content is served, its requests' items
+ * by a second persistent launch per admitted set), BUFFER_TOO_SMALL
  * (resident region full), HIP.
  */
 recoil_status recoil_server_add_content(recoil_server *server, const recoil_blob *blob, uint32_t *content_id);

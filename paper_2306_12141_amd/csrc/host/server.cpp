@@ -111,6 +111,8 @@ using RequestPtr = std::shared_ptr<Request>;
 
 // Control region of one launch slot (byte offsets): queue head, per-request
 // error words, per-request outstanding item counts, stream descriptors, work items.
+// The wide launch's queue head sits this many bytes after the first.
+constexpr uint64_t kWideHeadOffset = 128;
 struct CtrlLayout {
     uint64_t head = 0, err = 0, remaining = 0, descs = 0, items = 0, bytes = 0;
     CtrlLayout() = default;
@@ -393,7 +395,7 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
     std::memset(sl.done_host, 0, (size_t)k * 4);
     StreamDesc *descs = reinterpret_cast<StreamDesc *>(ctrl + L.descs);
     WorkItem *items = reinterpret_cast<WorkItem *>(ctrl + L.items);
-    uint32_t lut_bytes = 16;
+    uint32_t lut_bytes[2] = {16, 16};     // largest table of the one-level and of the wide requests
     uint64_t moff = 0;
     for (uint32_t i = 0; i < k; ++i) {
         const Request &r = *sl.reqs[i];
@@ -417,15 +419,25 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
         std::memcpy(meta + moff, r.plan.meta.data(), r.plan.meta.size() * sizeof(UnitMeta));
         std::memcpy(meta + moff + r.unit_bytes, r.plan.lanes.data(), r.plan.lanes.size() * 4);
         moff += r.meta_bytes;
-        lut_bytes = std::max(lut_bytes, ct.lut_bytes);
+        lut_bytes[b.quant_bits > 12] = std::max(lut_bytes[b.quant_bits > 12], ct.lut_bytes);
     }
-    // Largest request first, so the longest work starts first.
+    // Requests with one-level tables first, then those with two-level tables (13 <= n
+    // <= 16, a kernel of their own); in each, the largest request first, so the
+    // longest work starts first.
+    auto wide = [&](uint32_t i) { return sl.reqs[i]->content.blob->quant_bits > 12; };
     std::vector<uint32_t> order(k);
     for (uint32_t i = 0; i < k; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return sl.reqs[a]->c.out_bytes > sl.reqs[b]->c.out_bytes; });
-    uint64_t it = 0;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (wide(a) != wide(b)) return !wide(a);
+        return sl.reqs[a]->c.out_bytes > sl.reqs[b]->c.out_bytes;
+    });
+    uint64_t it = 0, n_plain = 0;
+    bool seen_wide = false;
     for (uint32_t i : order) {
+        if (wide(i) && !seen_wide) {
+            n_plain = it;
+            seen_wide = true;
+        }
         const Request &r = *sl.reqs[i];
         if (r.items == 0) continue;
         if (r.content.single_symbol) { items[it++] = WorkItem{i, 0, 1, 0}; continue; }
@@ -433,6 +445,7 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
             items[it++] = WorkItem{i, (uint32_t)f, (uint32_t)std::min<uint64_t>(r.per_item, r.pairs - f),
                                    r.single ? kItemSingle : 0u};
     }
+    if (!seen_wide) n_plain = it;
     unsigned char *a = s->arena;
     hipError_t e = hipMemcpyAsync(a + sl.ctrl_off, ctrl, ctrl_used, hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess && sl.meta_bytes)
@@ -448,11 +461,21 @@ hipError_t launch_slot(recoil_server *s, Slot &sl) {
     bp.err_stride = 1;
     bp.remaining = reinterpret_cast<uint32_t *>(a + sl.ctrl_off + L.remaining);
     bp.host_done = sl.done_dev;
-    bp.n_items = (uint32_t)n_items;
-    bp.lut_bytes = lut_bytes;
     const uint64_t t = clock_ns();
     for (RequestPtr &r : sl.reqs) r->c.t_launch_ns = t;
+    // One persistent launch for the one-level tables' items, then one for the wide
+    // tables' items with its own queue head (128 bytes on).
+    bp.n_items = (uint32_t)n_plain;
+    bp.lut_bytes = lut_bytes[0];
     e = launch_batch(bp, s->tuning, sl.stream);
+    if (e == hipSuccess && n_items > n_plain) {
+        bp.items += n_plain;
+        bp.head = reinterpret_cast<uint32_t *>(a + sl.ctrl_off + L.head + kWideHeadOffset);
+        bp.n_items = (uint32_t)(n_items - n_plain);
+        bp.lut_bytes = lut_bytes[1];
+        bp.wide = 1;
+        e = launch_batch(bp, s->tuning, sl.stream);
+    }
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     return e;
 }
@@ -609,7 +632,6 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
     if (bp->partitioned())   // requests ask for a unit count, which a partitioned stream cannot give
         return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: partitioned streams cannot be combined per request");
     if (bp->adaptive) return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: adaptive streams are decoded alone");
-    if (bp->quant_bits > 12) return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: n > 12 streams are decoded alone");
     PlanData probe;
     recoil_status st = build_units(bp, probe);   // checks the GPU decoder's limits
     if (st) return st;
@@ -619,7 +641,7 @@ recoil_status recoil_server_add_content(recoil_server *s, const recoil_blob *blo
     ct.lut_bytes = (uint32_t)probe.lut.size();
     ct.single_symbol = probe.single_symbol;
     ct.fill_symbol = probe.fill_symbol;
-    if (batch_blocks_per_cu(s->tuning, ct.lut_bytes) < 1)
+    if (batch_blocks_per_cu(s->tuning, ct.lut_bytes, bp->quant_bits > 12) < 1)
         return fail(RECOIL_ERR_UNSUPPORTED, "server_add_content: decode table does not fit the launch shape");
     const uint64_t wbytes = words_section_bytes(bp->n_words());
     {

@@ -220,16 +220,15 @@ def test_full_size_requests(rc, big_corpus):
 
 
 def test_add_content_refuses_streams_decoded_alone(rc, corpus):
-    """Conventional partitioned, adaptive and n > 12 streams are refused at
-    add_content with RECOIL_ERR_UNSUPPORTED; the server keeps serving."""
+    """Conventional partitioned and adaptive streams are refused at add_content with
+    RECOIL_ERR_UNSUPPORTED; the server keeps serving."""
     srv, ids = _server(rc, corpus, 16 << 20)
     try:
         s = synth.draw_symbols(synth.zipf_pmf(256, 1.1), 6400, 100_000, np.uint8)
         pmfs, tidx, sa = synth.adaptive_stream(6401, 100_000, 4, 64)
         tabs = np.stack([rc.quantize((pmf * (1 << 30)).astype(np.uint64) + 1, 10) for pmf in pmfs])
         refused = [rc.encode_partitioned(s, lanes=32, quant_bits=11, partitions=8),
-                   rc.encode_adaptive(sa, tabs, tidx, lanes=32, quant_bits=10, splits=16, alphabet=64),
-                   rc.encode(s, lanes=32, quant_bits=16, splits=16)]
+                   rc.encode_adaptive(sa, tabs, tidx, lanes=32, quant_bits=10, splits=16, alphabet=64)]
         for b in refused:
             with pytest.raises(rc.RecoilError) as e:
                 srv.add_content(b)
@@ -237,5 +236,27 @@ def test_add_content_refuses_streams_decoded_alone(rc, corpus):
         rid = srv.submit(ids[0], 3, tag=0)
         _check(srv, corpus, _drain(srv, 1)[rid])
         srv.release(rid)
+    finally:
+        srv.close()
+
+
+def test_wide_table_content(rc, corpus):
+    """Content coded at 13 <= n <= 16 served beside one-level content: each launch
+    runs the wide requests' items in a second persistent kernel."""
+    wide = []
+    for i, (W, n, dt, A) in enumerate([(32, 16, np.uint8, 256), (64, 14, np.uint8, 256), (32, 16, np.uint16, 2000)]):
+        s = synth.draw_symbols(synth.zipf_pmf(A, 1.2), 6600 + i, 200_003 + 311 * i, dt)
+        wide.append((s, rc.encode(s, lanes=W, quant_bits=n, splits=64, alphabet=A)))
+    allc = list(corpus) + wide
+    srv, ids = _server(rc, allc, 64 << 20)
+    try:
+        rids = []
+        for rep in range(3):
+            for cid in ids:
+                rids.append(srv.submit(cid, (3, 0, 17)[rep], tag=cid))
+        got = _drain(srv, len(rids))
+        for rid in rids:
+            _check(srv, allc, got[rid])
+            srv.release(rid)
     finally:
         srv.close()
