@@ -11,7 +11,8 @@ The same line also carries (each bit-exact against the input symbols):
   extras: the stream at W = 32, every split point used, a decode after evicting
       the caches, the W = 32 stream combined to 16384 / 4096 / 1024 / 256 splits,
       the same stream coded by the conventional partitioning baseline (Sec. 2.3) at
-      65536 / 16384 / 256 sub-sequences against Recoil at the same parallelism,
+      65536 / 16384 / 2176 / 256 / 16 sub-sequences against Recoil at the same
+      parallelism (2176 and 16: the paper's Large and Small variations),
       adaptive coding (16 per-symbol tables) against one static table on the same
       symbols, the headline stream coded at n = 16 (two-level table), the split
       metadata unpacked on the device against the host planner, the host encode
@@ -494,7 +495,7 @@ def run_conventional(args, base, torch, np, rc):
     (what a client receives) and decoded GB/s."""
     s, recoil_blob, spec = base["symbols"], base["blob"], base["spec"]
     rows = []
-    for P in (65536, 16384, 256):
+    for P in (65536, 16384, 2176, 256, 16):   # 2176 and 16: the Large and Small variations of Tables 5-6
         b = rc.encode_partitioned(s, lanes=spec.lanes, quant_bits=spec.quant_bits, partitions=P)
         info = b.info
         plan = rc.Plan(b)
