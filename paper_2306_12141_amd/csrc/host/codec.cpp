@@ -328,11 +328,24 @@ void choose_splits_parallel(BlobData &b, const EventLog &log, uint32_t M, uint32
     const uint64_t B = log.sym.size();
     const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(threads, B / 4096 + 1));
     auto chunk_lo = [&](uint32_t c) { return B * c / chunks; };
+    // Chunk c on a thread of its own (chunk 0 on the caller's). A thread that cannot
+    // be started leaves its chunks to the caller; a failure inside a chunk is
+    // reported once every thread has been joined.
     auto run = [&](auto &&fn) {
+        std::atomic<bool> failed{false};
+        auto body = [&](uint32_t c) {
+            try { fn(c); } catch (...) { failed = true; }
+        };
         std::vector<std::thread> ts;
-        for (uint32_t c = 1; c < chunks; ++c) ts.emplace_back(fn, c);
-        fn(0u);
+        uint32_t c = 1;
+        try {
+            for (; c < chunks; ++c) ts.emplace_back(body, c);
+        } catch (...) {
+        }
+        for (uint32_t r = c; r < chunks; ++r) body(r);
+        body(0u);
         for (std::thread &t : ts) t.join();
+        if (failed) throw std::bad_alloc();
     };
     // Pass 1: each lane's latest event inside each chunk.
     std::vector<int64_t> last((size_t)chunks * W, -1);

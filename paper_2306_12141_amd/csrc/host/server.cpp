@@ -219,7 +219,12 @@ void prep_loop(recoil_server *s) {
             r = std::move(s->prep_q.front());
             s->prep_q.pop_front();
         }
-        prepare(*r);
+        try {
+            prepare(*r);
+        } catch (...) {   // host memory exhausted while combining: the request fails, the server goes on
+            r->c.status = RECOIL_ERR_OUT_OF_MEMORY;
+            r->ready.store(-1, std::memory_order_release);
+        }
         { std::lock_guard<std::mutex> lk(s->mu); }
         s->cv_launcher.notify_one();
     }
