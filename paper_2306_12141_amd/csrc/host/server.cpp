@@ -516,7 +516,12 @@ void launcher_loop(recoil_server *s) {
                 s->n_launched += free_slot->reqs.size();
                 ++s->n_in_flight;
                 lk.unlock();
-                const hipError_t e = launch_slot(s, *free_slot);
+                hipError_t e;
+                try {
+                    e = launch_slot(s, *free_slot);
+                } catch (...) {   // host memory exhausted while staging the set
+                    e = hipErrorOutOfMemory;
+                }
                 if (e != hipSuccess) {
                     // Nothing (or only part) was enqueued: fail the set and wait for the stream to drain.
                     (void)hipStreamSynchronize(free_slot->stream);
