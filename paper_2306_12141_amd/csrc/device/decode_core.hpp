@@ -180,6 +180,12 @@ struct PairDecoder {
     using Chunk = typename G::Chunk;
     static constexpr uint32_t S = G::S, C = G::C, R = G::R;
     static constexpr bool COUNT = VAR == kCount, ADAPT = VAR == kAdaptive;
+    // Fast-body stores of byte symbols four groups at a time (see store_quad), for
+    // 32-lane units: there a byte store writes only 32 bytes per unit, and one
+    // dword store per four groups decoded W = 32 streams 13-16 % faster, while at
+    // W = 64 the transpose's seven VALU per four groups cost more than the three
+    // stores they save (1 % slower).
+    static constexpr bool QUAD = W == 32 && sizeof(Sym) == 1 && K % 4 == 0;
     static_assert(!ADAPT || sizeof(Sym) == 1, "adaptive decoding reads the table index at the symbol's byte offset");
 
     const DecodeParams &p;
@@ -215,6 +221,7 @@ struct PairDecoder {
     uint32_t tready = 0;
     uint32_t x, rec, act, lim;
     uint32_t my_top, my_ghi, my_steps, lane_off;
+    uint32_t quad_off;     // QUAD: this lane's dword offset from the fast body's group pointer, plus 3W
     bool active;
 
     __device__ PairDecoder(const DecodeParams &p_, uint32_t lut_, uint32_t ring0_, uint32_t lane_)
@@ -308,6 +315,9 @@ struct PairDecoder {
         my_steps = S == 2 && upper ? steps[S - 1] : steps[0];
         // Fast-body store offset of this lane from unit 0's group pointer.
         lane_off = (coder + (S == 2 ? upper * W * (my_top - top0) : 0u)) * (uint32_t)sizeof(Sym);
+        // Lane 4a + b of a quad writes group b of a block of four, at the column of
+        // the quad's highest lane (its lowest coder): 3 - b columns below its own.
+        quad_off = lane_off - 3u + (lane & 3u) + (3u - (lane & 3u)) * W;
         const uint32_t mine = r0 + upper;
         const bool my_valid = mine < p.runs;
         const uint32_t my_hi = my_valid ? min(mine * p.run + p.run, p.units) - 1u : 0u;
@@ -402,15 +412,47 @@ struct PairDecoder {
         }
     }
 
+    // Byte symbols of groups G0 .. G0 + 3 (the low bytes of v[0..3]) written as one
+    // dword per lane: the four lanes of a quad hold four adjacent coders, so a 4 x 4
+    // byte transpose across the quad (two DPP swaps, each followed by a byte
+    // permute) leaves in lane 4a + b the four symbols of group G0 + b for coders
+    // W-4-4a .. W-1-4a, in address order. One store per four groups replaces four
+    // byte stores; the bytes written are the same.
+    template <uint32_t G0>
+    __device__ inline void store_quad(unsigned char *outh, const uint32_t (&v)[4]) const {
+        const uint32_t b = lane & 3u;
+        // d: byte j = this lane's symbol of group G0 + j.
+        const uint32_t d = __builtin_amdgcn_perm(__builtin_amdgcn_perm(v[3], v[2], 0x00000400u),
+                                                 __builtin_amdgcn_perm(v[1], v[0], 0x00000400u), 0x05040100u);
+        // Swap 16-bit halves with lane b ^ 2: lanes 0, 1 keep groups 0-1, lanes 2, 3 groups 2-3.
+        const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0x4E, 0xF, 0xF, false);
+        const uint32_t h = __builtin_amdgcn_perm(p2, d, (b & 2u) ? 0x03020706u : 0x05040100u);
+        // Swap bytes with lane b ^ 1 and order the coders upwards in address.
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)h, 0xB1, 0xF, 0xF, false);
+        const uint32_t t = __builtin_amdgcn_perm(p1, h, (b & 1u) ? 0x05010703u : 0x00040206u);
+        unsigned char *dst = outh + quad_off - (G0 + 3) * W;
+        *reinterpret_cast<uint32_t *>(dst) = t;
+        if constexpr (COUNT) {
+            const uint64_t i = (uint64_t)(dst - static_cast<unsigned char *>(p.out));
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) count_store(i + j);
+        }
+    }
+
     template <uint32_t G_IDX>
-    __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh) {
+    __device__ inline void group_fast(uint32_t &a, uint32_t &e, unsigned char *outh, uint32_t (&held)[4]) {
         read_step<G_IDX>(x < kL, a, e);
         uint32_t s;
         if constexpr (ADAPT) s = T::step_t(lut, x, n, mask, tcur[G_IDX]);
         else s = T::step(lut, x, n, mask);
-        unsigned char *dst = outh + lane_off - G_IDX * W * sizeof(Sym);
-        *reinterpret_cast<Sym *>(dst) = (Sym)s;
-        if constexpr (COUNT) count_store((uint64_t)(dst - static_cast<unsigned char *>(p.out)) / sizeof(Sym));
+        if constexpr (QUAD) {
+            held[G_IDX & 3u] = s;
+            if constexpr ((G_IDX & 3u) == 3u) store_quad<G_IDX - 3u>(outh, held);
+        } else {
+            unsigned char *dst = outh + lane_off - G_IDX * W * sizeof(Sym);
+            *reinterpret_cast<Sym *>(dst) = (Sym)s;
+            if constexpr (COUNT) count_store((uint64_t)(dst - static_cast<unsigned char *>(p.out)) / sizeof(Sym));
+        }
     }
 
     __device__ inline void count_store(uint64_t i) const { atomicAdd(p.counts + i, 1u); }
@@ -474,7 +516,8 @@ struct PairDecoder {
             (group_sync<G_IDX>(k + G_IDX, a, e), ...);
         } else {
             unsigned char *outh = static_cast<unsigned char *>(p.out) + (uint64_t)(top0 - k) * W * sizeof(Sym);
-            (group_fast<G_IDX>(a, e, outh), ...);
+            uint32_t held[4];
+            (group_fast<G_IDX>(a, e, outh, held), ...);
         }
     }
 
