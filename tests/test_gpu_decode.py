@@ -183,6 +183,27 @@ def test_waves_per_workgroup(rc, W, splits, dt):
         assert np.array_equal(gpu_decode(rc, blob, waves=w, chunk_groups=k), s)
 
 
+@pytest.mark.parametrize("N,M", [((1 << 22) + 77, 20_000), ((1 << 20) + 5, 300), (70_001, 12)])
+def test_w32_byte_symbols_every_shape(rc, N, M):
+    """32-lane units store byte symbols one dword per four groups (a byte transpose
+    across each quad of lanes): every launch shape (1, 8 and 16 waves; 4- and 8-group
+    super-steps; runs of 1, 3 and automatic length; one unit or a pair per wave)
+    decodes the input, ragged last group included."""
+    s = _syms(4400 + M, N, 256, np.uint8, 1.1)
+    blob = rc.encode(s, lanes=32, quant_bits=12, splits=M, alphabet=256)
+    per_wave = set()
+    for w, k, r in itertools.product((1, 8, 16), (4, 8), (0, 1, 3)):
+        _say("case w32 byte symbols", N, M, w, k, r)
+        plan = rc.Plan(blob)
+        plan.set_tuning(waves=w, chunk_groups=k, units_per_run=r)
+        per_wave.add(plan.shape().units_per_wave)
+        assert np.array_equal(gpu_decode(rc, blob, waves=w, chunk_groups=k, units_per_run=r), s)
+    if M == 20_000:
+        assert 2 in per_wave    # 20000 runs of one unit exceed the resident waves: the pair kernel
+    if M == 12:
+        assert per_wave == {1}
+
+
 def test_plan_autotune(rc):
     """The single-stream autotuner leaves a valid shape on the plan, the decode with it
     is exact, and a second plan of the same shape is served from the cache."""
